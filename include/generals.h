@@ -1,0 +1,195 @@
+/*
+ * generals.h -- C ABI of the MI355X (gfx950) batched Generals.io environment
+ * step, after arxiv 2606.23348 ("Superhuman AI for Generals.io Using
+ * Self-Play Reinforcement Learning"), Section IV (game description) and
+ * Section IV-G (the batched environment, Table I).
+ *
+ * Conventions for every entry point:
+ *  - Returns a gen_status; GEN_OK == 0.  On any other value a message is
+ *    available from gen_last_error() on the calling thread.  Nothing is
+ *    launched when an argument check fails.
+ *  - "d_" pointers are device pointers (HIP device memory) owned by the
+ *    caller; "h_" pointers are host memory owned by the caller.  The library
+ *    never frees caller memory and allocates no device memory in the plain
+ *    entry points.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Launches are asynchronous on that stream unless a call says it blocks.
+ *    Asynchronous kernel faults surface as GEN_EHIP on a later call.
+ *  - Action codes follow the paper's H x W x 9 action space (Section IV-G):
+ *    a = cell * 9 + k, cell = row * W + col; k = 0 pass, k = 1..4 send
+ *    all-but-one unit up/down/left/right, k = 5..8 send half (rounded down)
+ *    up/down/left/right.  Any code that is out of range, has k = 0, or is
+ *    illegal under the rules (Section IV-D) is a pass, never an error.
+ *  - Players: 2 in 1v1, 4 in 2v2 (team = id mod 2), 2..8 in free-for-all.
+ *  - All arithmetic is exact integer arithmetic; army additions saturate at
+ *    INT32_MAX.
+ */
+#ifndef GENERALS_H
+#define GENERALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEN_LAYOUT_VERSION 1
+#define GEN_MAX_PLAYERS 8
+#define GEN_MIN_SIDE 3
+#define GEN_MAX_SIDE 32
+#define GEN_MAX_CELLS 1024
+#define GEN_OBS_CHANNELS 8
+
+typedef enum gen_status {
+    GEN_OK = 0,
+    GEN_EINVAL = -1,    /* bad argument, shape, mode or state contents */
+    GEN_ENOMEM = -2,    /* a caller buffer is too small, or a host allocation failed */
+    GEN_EHIP = -3,      /* the HIP runtime reported an error */
+    GEN_EBUDGET = -4,   /* admission refused: the device-memory budget is exhausted */
+    GEN_EBUSY = -5,     /* not finished yet (wait with a timeout) */
+    GEN_ENOTFOUND = -6  /* unknown handle or ticket */
+} gen_status;
+
+/* Game formats (Section IV-E). */
+typedef enum gen_mode { GEN_1V1 = 0, GEN_2V2 = 1, GEN_FFA = 2 } gen_mode;
+
+/* Cell types (Section IV-A: plain, mountain, castle, general). */
+enum { GEN_PLAIN = 0, GEN_MOUNTAIN = 1, GEN_CASTLE = 2, GEN_GENERAL = 3 };
+
+/* Observation channels, uint8 [E][P][8][H][W] (8-channel reduction of the
+ * paper's Appendix A feature tensor; fog as in Section IV-B): */
+enum {
+    GEN_OBS_OWN = 0,       /* cell owned by the observing player */
+    GEN_OBS_ENEMY = 1,     /* visible, owned by a player outside the observer's team */
+    GEN_OBS_NEUTRAL = 2,   /* visible, unowned, not a mountain */
+    GEN_OBS_MOUNTAIN = 3,  /* visible mountain */
+    GEN_OBS_CASTLE = 4,    /* visible castle (city) */
+    GEN_OBS_GENERAL = 5,   /* visible general */
+    GEN_OBS_FOG = 6,       /* not visible */
+    GEN_OBS_ARMY = 7       /* visible army, clamped to 255; 0 under fog */
+};
+
+/* Map-generator and episode parameters (Section IV-A generator family). */
+typedef struct gen_params {
+    int32_t n_players;          /* FFA: 2..8.  Ignored for 1v1 (2) and 2v2 (4). */
+    uint32_t mountain_thresh;   /* a cell is a mountain iff its 32-bit draw < thresh
+                                   (floor(2^32 * density); 858993459 for 20%) */
+    int32_t cities_min, cities_max;       /* neutral castles per map, inclusive */
+    int32_t city_army_min, city_army_max; /* their starting armies, inclusive */
+    int32_t min_general_dist;   /* Manhattan distance between any two generals */
+    int32_t auto_reset;         /* 1: a finished game restarts on the next map in the same step */
+    int32_t pregrow;            /* 1: at episode 0, envs with global id % 4 == 0 start
+                                   each general at 100000 + U{0..900000} */
+    int32_t reserved[7];        /* must be zero */
+} gen_params;
+
+/* Descriptor of one batch of identical envs living in one device buffer.
+ * Filled by gen_layout() / gen_reset(); the caller keeps it and passes it to
+ * every later call.  It holds no device resources. */
+typedef struct gen_state {
+    uint32_t version;           /* GEN_LAYOUT_VERSION */
+    int32_t n_envs, H, W, mode, n_players;
+    int32_t stride;             /* cells per env in the grid arrays: H*W rounded up to 16 */
+    int32_t reserved0;
+    uint64_t seed;              /* map seed: draws of every (re)generated map */
+    uint64_t env_base;          /* global id of env 0 (keys every random draw) */
+    gen_params params;
+    /* Device buffer layout (bytes from d_buf), struct-of-arrays, env-major:
+     *   scalars [n_envs] 32-byte records {int32 turn; uint32 episode;
+     *           uint8 alive_mask; uint8 finished; uint8 pad[6]; int16 gpos[8]; }
+     *   owner   int8  [n_envs][stride]  (-1 neutral)
+     *   type    uint8 [n_envs][stride]
+     *   army    int32 [n_envs][stride]
+     * Cells past H*W in a row are padding (neutral plain, 0 units). */
+    uint64_t off_scalars, off_owner, off_type, off_army;
+    uint64_t bytes;             /* device bytes the buffer must hold */
+    void *d_buf;                /* device buffer (set by gen_reset) */
+} gen_state;
+
+/* Host copy of a batch in the public host-state format (all C-contiguous,
+ * caller-owned):  owner int8 [E][H*W], army int32 [E][H*W], type uint8
+ * [E][H*W], turn int32 [E], episode uint32 [E], alive uint8 [E] (bit p set
+ * while player p has a general), finished uint8 [E] (1 once a game ended
+ * with auto_reset off; such an env is frozen), gpos int16 [E][P]. */
+typedef struct gen_host_state {
+    int8_t *owner;
+    int32_t *army;
+    uint8_t *type;
+    int32_t *turn;
+    uint32_t *episode;
+    uint8_t *alive;
+    uint8_t *finished;
+    int16_t *gpos;
+} gen_host_state;
+
+/* Library version (GEN_LAYOUT_VERSION of the build). */
+int gen_version(void);
+
+/* Message of the last non-OK return on this thread ("" if none).  The
+ * pointer stays valid until the next call on the same thread. */
+const char *gen_last_error(void);
+
+/* Defaults of the paper's generator (Section IV-A): 20% mountains, 9..11
+ * castles of 40..50 units, generals at least 9 apart, auto-reset on. */
+int gen_default_params(int32_t mode, int32_t n_players, gen_params *out);
+
+/* Compute the device layout of n_envs envs of H x W (3..32 each side) in
+ * `mode` without touching the device.  params NULL = defaults.  Fills *out
+ * (d_buf = NULL).  GEN_EINVAL on a bad shape, mode or parameter. */
+int gen_layout(int32_t n_envs, int32_t H, int32_t W, int32_t mode, const gen_params *params,
+               uint64_t seed, gen_state *out);
+
+/* Device bytes needed for such a batch (0 on invalid input). */
+uint64_t gen_state_bytes(int32_t n_envs, int32_t H, int32_t W, int32_t mode, const gen_params *params);
+
+/* Generate fresh maps (Section IV-A; randomness only in the initial state,
+ * Section III) for envs env_base .. env_base+n_envs-1 at episode 0 into
+ * d_buf (buf_bytes >= gen_state_bytes, 256-byte aligned), fill *out, and, if
+ * d_obs is not NULL, write the initial observation uint8 [E][P][8][H][W].
+ * GEN_ENOMEM if buf_bytes is too small. */
+int gen_reset(uint64_t seed, uint64_t env_base, int32_t n_envs, int32_t H, int32_t W, int32_t mode,
+              const gen_params *params, void *d_buf, uint64_t buf_bytes, uint8_t *d_obs, void *stream,
+              gen_state *out);
+
+/* One environment step of every env (Sections IV-B..IV-E): moves in
+ * rotating priority, combat, general capture and land transfer, growth,
+ * terminal rewards, optional auto-reset, fog and observation.
+ *   d_actions  int32 [E][P]   (read)
+ *   d_obs      uint8 [E][P][8][H][W]  (written; after an auto-reset this is
+ *              the new map's observation)
+ *   d_rewards  int32 [E][P]   (written: +1 win, -1 loss, else 0)
+ *   d_dones    uint8 [E]      (written: 1 when the game ended on this step,
+ *              or was already over and frozen)
+ *   d_land     int32 [E][P]   (nullable; scoreboard land, Section IV-B)
+ *   d_army     int64 [E][P]   (nullable; scoreboard army total) */
+int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int32_t *d_rewards,
+             uint8_t *d_dones, int32_t *d_land, int64_t *d_army, void *stream);
+
+/* Random legal actor: for every env and living player, draw 0 of Philox
+ * key (actor_seed, 2), counter (env_base + e, step_idx, player, 0) picks
+ * uniformly among [pass] + the legal (cell, k) moves listed by cell in
+ * row-major order, then k = 1..8.  Dead players pass.  d_actions int32 [E][P]. */
+int gen_sample_actions(const gen_state *st, uint64_t actor_seed, uint64_t step_idx, int32_t *d_actions,
+                       void *stream);
+
+/* Observation of the current state (no state change). */
+int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
+
+/* Blocking copies between the device buffer and the public host format
+ * (synchronises `stream`).  gen_set_state rejects (GEN_EINVAL) contents the
+ * kernels cannot take: owner outside [-1, P), type outside [0, 3], negative
+ * army, gpos outside the grid, alive bits beyond P, negative turn. */
+int gen_get_state(const gen_state *st, gen_host_state *h, void *stream);
+int gen_set_state(const gen_state *st, const gen_host_state *h, void *stream);
+
+/* Blocking copy of selected envs only: env h_env_ids[i] (0 <= id < n_envs)
+ * goes to row i of each host array, which therefore hold n_ids rows.  For
+ * checkpoints of part of a batch and for sampled parity checks. */
+int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENERALS_H */

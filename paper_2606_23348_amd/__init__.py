@@ -1,0 +1,246 @@
+"""MI355X (gfx950) batched Generals.io environment step -- Python binding.
+
+A thin ctypes layer over ``libgenerals.so`` (declared in ``include/generals.h``)
+with the same function names.  It only marshals arguments: torch tensors
+supply device memory (``data_ptr``) and HIP streams (``cuda_stream``); every
+step of the environment runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgenerals.so")
+
+GEN_OK, GEN_EINVAL, GEN_ENOMEM, GEN_EHIP, GEN_EBUDGET, GEN_EBUSY, GEN_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+GEN_1V1, GEN_2V2, GEN_FFA = 0, 1, 2
+GEN_PLAIN, GEN_MOUNTAIN, GEN_CASTLE, GEN_GENERAL = 0, 1, 2, 3
+GEN_LAYOUT_VERSION = 1
+
+
+class GenError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gen error {code}: {msg}")
+        self.code = code
+
+
+class gen_params(ctypes.Structure):
+    _fields_ = [("n_players", ctypes.c_int32), ("mountain_thresh", ctypes.c_uint32),
+                ("cities_min", ctypes.c_int32), ("cities_max", ctypes.c_int32),
+                ("city_army_min", ctypes.c_int32), ("city_army_max", ctypes.c_int32),
+                ("min_general_dist", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
+                ("pregrow", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class gen_state(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_uint32), ("n_envs", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("mode", ctypes.c_int32), ("n_players", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("env_base", ctypes.c_uint64), ("params", gen_params),
+                ("off_scalars", ctypes.c_uint64), ("off_owner", ctypes.c_uint64),
+                ("off_type", ctypes.c_uint64), ("off_army", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("d_buf", ctypes.c_void_p)]
+
+
+class gen_host_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("owner", "army", "type", "turn", "episode", "alive", "finished", "gpos")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgenerals.so (torch first, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- loads the HIP runtime the library binds to
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(python -m paper_2606_23348_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+    P = ctypes.POINTER
+    L.gen_version.argtypes, L.gen_version.restype = [], ctypes.c_int
+    L.gen_last_error.argtypes, L.gen_last_error.restype = [], ctypes.c_char_p
+    L.gen_default_params.argtypes = [i32, i32, P(gen_params)]
+    L.gen_layout.argtypes = [i32, i32, i32, i32, P(gen_params), u64, P(gen_state)]
+    L.gen_state_bytes.argtypes, L.gen_state_bytes.restype = [i32, i32, i32, i32, P(gen_params)], u64
+    L.gen_reset.argtypes = [u64, u64, i32, i32, i32, i32, P(gen_params), vp, u64, vp, vp, P(gen_state)]
+    L.gen_step.argtypes = [P(gen_state), vp, vp, vp, vp, vp, vp, vp]
+    L.gen_sample_actions.argtypes = [P(gen_state), u64, u64, vp, vp]
+    L.gen_observe.argtypes = [P(gen_state), vp, vp]
+    L.gen_get_state.argtypes = [P(gen_state), P(gen_host_state), vp]
+    L.gen_set_state.argtypes = [P(gen_state), P(gen_host_state), vp]
+    L.gen_get_envs.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
+    for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_sample_actions",
+              "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def gen_last_error() -> str:
+    return lib().gen_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != GEN_OK:
+        raise GenError(rc, gen_last_error())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def gen_version() -> int:
+    return lib().gen_version()
+
+
+def gen_default_params(mode: int, n_players: int = 0) -> gen_params:
+    p = gen_params()
+    _check(lib().gen_default_params(mode, n_players, ctypes.byref(p)))
+    return p
+
+
+def make_params(mode: int, n_players: int = 0, **kw) -> gen_params:
+    """Defaults for `mode`, overridden by keyword fields of gen_params."""
+    p = gen_default_params(mode, n_players if mode == GEN_FFA else 0)
+    for k, v in kw.items():
+        if k == "n_players":
+            continue
+        setattr(p, k, int(v))
+    return p
+
+
+def gen_layout(n_envs: int, H: int, W: int, mode: int, params: gen_params | None = None,
+               seed: int = 0) -> gen_state:
+    st = gen_state()
+    _check(lib().gen_layout(n_envs, H, W, mode, ctypes.byref(params) if params else None, seed,
+                            ctypes.byref(st)))
+    return st
+
+
+def gen_state_bytes(n_envs: int, H: int, W: int, mode: int, params: gen_params | None = None) -> int:
+    return int(lib().gen_state_bytes(n_envs, H, W, mode, ctypes.byref(params) if params else None))
+
+
+def gen_reset(seed: int, env_base: int, n_envs: int, H: int, W: int, mode: int, params: gen_params | None,
+              buf, obs=None, stream=None) -> gen_state:
+    st = gen_state()
+    _check(lib().gen_reset(seed, env_base, n_envs, H, W, mode, ctypes.byref(params) if params else None,
+                           _ptr(buf), buf.numel() * buf.element_size(), _ptr(obs), _stream(stream),
+                           ctypes.byref(st)))
+    st._keep = buf  # the descriptor refers to this tensor's memory
+    return st
+
+
+def gen_step(st: gen_state, actions, obs, rewards, dones, land=None, army=None, stream=None):
+    _check(lib().gen_step(ctypes.byref(st), _ptr(actions), _ptr(obs), _ptr(rewards), _ptr(dones),
+                          _ptr(land), _ptr(army), _stream(stream)))
+
+
+def gen_sample_actions(st: gen_state, actor_seed: int, step_idx: int, actions, stream=None):
+    _check(lib().gen_sample_actions(ctypes.byref(st), actor_seed, step_idx, _ptr(actions), _stream(stream)))
+
+
+def gen_observe(st: gen_state, obs, stream=None):
+    _check(lib().gen_observe(ctypes.byref(st), _ptr(obs), _stream(stream)))
+
+
+def _host_arrays(E: int, HW: int, P: int) -> dict:
+    return {
+        "owner": np.zeros((E, HW), np.int8), "army": np.zeros((E, HW), np.int32),
+        "type": np.zeros((E, HW), np.uint8), "turn": np.zeros(E, np.int32),
+        "episode": np.zeros(E, np.uint32), "alive": np.zeros(E, np.uint8),
+        "finished": np.zeros(E, np.uint8), "gpos": np.zeros((E, P), np.int16),
+    }
+
+
+_HOST_TYPES = {"owner": np.int8, "army": np.int32, "type": np.uint8, "turn": np.int32,
+               "episode": np.uint32, "alive": np.uint8, "finished": np.uint8, "gpos": np.int16}
+
+
+def _host_struct(h: dict) -> gen_host_state:
+    for k, dt in _HOST_TYPES.items():
+        a = h[k]
+        if a.dtype != dt or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError(f"host state field {k} must be C-contiguous {np.dtype(dt).name}")
+    return gen_host_state(*(h[k].ctypes.data for k in _HOST_TYPES))
+
+
+def gen_get_state(st: gen_state, stream=None) -> dict:
+    """Blocking copy of the device state into the public host format (numpy)."""
+    h = _host_arrays(st.n_envs, st.H * st.W, st.n_players)
+    hs = _host_struct(h)
+    _check(lib().gen_get_state(ctypes.byref(st), ctypes.byref(hs), _stream(stream)))
+    return h
+
+
+def gen_get_envs(st: gen_state, env_ids, stream=None) -> dict:
+    """Blocking copy of the listed envs (row i = env env_ids[i])."""
+    ids = np.ascontiguousarray(np.asarray(env_ids, np.int32))
+    h = _host_arrays(len(ids), st.H * st.W, st.n_players)
+    hs = _host_struct(h)
+    _check(lib().gen_get_envs(ctypes.byref(st), ids.ctypes.data, len(ids), ctypes.byref(hs), _stream(stream)))
+    return h
+
+
+def gen_set_state(st: gen_state, h: dict, stream=None):
+    hs = _host_struct(h)
+    _check(lib().gen_set_state(ctypes.byref(st), ctypes.byref(hs), _stream(stream)))
+
+
+class Batch:
+    """Device tensors of one batch of identical envs (torch allocates; the
+    library computes).  Convenience only: every method is one library call."""
+
+    def __init__(self, n_envs: int, H: int, W: int, mode: int, params: gen_params | None = None,
+                 seed: int = 0, env_base: int = 0, device: str = "cuda", with_obs: bool = True,
+                 scoreboard: bool = False, stream=None):
+        import torch
+        lay = gen_layout(n_envs, H, W, mode, params, seed)
+        P = lay.n_players
+        self.n_envs, self.H, self.W, self.mode, self.P = n_envs, H, W, mode, P
+        self.buf = torch.empty(lay.bytes, dtype=torch.uint8, device=device)
+        self.obs = torch.empty((n_envs, P, 8, H, W), dtype=torch.uint8, device=device) if with_obs else None
+        self.actions = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
+        self.rewards = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
+        self.dones = torch.zeros(n_envs, dtype=torch.uint8, device=device)
+        self.land = torch.zeros((n_envs, P), dtype=torch.int32, device=device) if scoreboard else None
+        self.army = torch.zeros((n_envs, P), dtype=torch.int64, device=device) if scoreboard else None
+        self.st = gen_reset(seed, env_base, n_envs, H, W, mode, params, self.buf, self.obs, stream)
+
+    def sample(self, actor_seed: int, step_idx: int, stream=None):
+        gen_sample_actions(self.st, actor_seed, step_idx, self.actions, stream)
+
+    def step(self, stream=None):
+        gen_step(self.st, self.actions, self.obs, self.rewards, self.dones, self.land, self.army, stream)
+
+    def observe(self, stream=None):
+        gen_observe(self.st, self.obs, stream)
+
+    def get_state(self, stream=None) -> dict:
+        return gen_get_state(self.st, stream)
+
+    def get_envs(self, env_ids, stream=None) -> dict:
+        return gen_get_envs(self.st, env_ids, stream)
+
+    def set_state(self, h: dict, stream=None):
+        gen_set_state(self.st, h, stream)

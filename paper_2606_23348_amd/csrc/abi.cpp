@@ -1,0 +1,392 @@
+// abi.cpp -- the extern "C" boundary of libgenerals.so: argument checks,
+// device layout, launches, host-format copies and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/generals.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return GEN_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GEN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+int players_of(int32_t mode, int32_t n_players)
+{
+    if (mode == GEN_1V1) return 2;
+    if (mode == GEN_2V2) return 4;
+    if (mode == GEN_FFA) return n_players;
+    return -1;
+}
+
+int check_params(const gen_params &p, int P, int HW)
+{
+    if (p.cities_min < 0 || p.cities_max < p.cities_min || p.cities_max > HW)
+        return fail(GEN_EINVAL, "cities range [%d, %d] invalid", p.cities_min, p.cities_max);
+    if (p.city_army_min < 0 || p.city_army_max < p.city_army_min)
+        return fail(GEN_EINVAL, "city army range [%d, %d] invalid", p.city_army_min, p.city_army_max);
+    if (p.min_general_dist < 0 || p.min_general_dist > 64)
+        return fail(GEN_EINVAL, "min_general_dist %d outside [0, 64]", p.min_general_dist);
+    if ((p.auto_reset != 0 && p.auto_reset != 1) || (p.pregrow != 0 && p.pregrow != 1))
+        return fail(GEN_EINVAL, "auto_reset and pregrow must be 0 or 1");
+    for (int i = 0; i < 7; ++i)
+        if (p.reserved[i] != 0) return fail(GEN_EINVAL, "gen_params.reserved must be zero");
+    (void)P;
+    return GEN_OK;
+}
+
+gen::Geom geom_of(const gen_state &st)
+{
+    gen::Geom g;
+    g.H = st.H;
+    g.W = st.W;
+    g.HW = st.H * st.W;
+    g.S = st.stride;
+    g.P = st.n_players;
+    g.mode = st.mode;
+    g.NW = (g.HW + 63) / 64;
+    g.magic_w = (uint32_t)(((1u << 20) + (uint32_t)st.W - 1) / (uint32_t)st.W);
+    g.magic_hw = (uint32_t)(((uint64_t(1) << 32) + (uint64_t)g.HW - 1) / (uint64_t)g.HW);
+    return g;
+}
+
+gen::GenParamsDev prm_of(const gen_params &p)
+{
+    gen::GenParamsDev d;
+    d.thresh = p.mountain_thresh;
+    d.cmin = p.cities_min;
+    d.cmax = p.cities_max;
+    d.amin = p.city_army_min;
+    d.amax = p.city_army_max;
+    d.dmin = p.min_general_dist;
+    d.auto_reset = p.auto_reset;
+    d.pregrow = p.pregrow;
+    return d;
+}
+
+int check_state(const gen_state *st)
+{
+    if (st == nullptr) return fail(GEN_EINVAL, "state descriptor is NULL");
+    if (st->version != GEN_LAYOUT_VERSION)
+        return fail(GEN_EINVAL, "state descriptor version %u, library expects %u", st->version, GEN_LAYOUT_VERSION);
+    if (st->d_buf == nullptr) return fail(GEN_EINVAL, "state descriptor has no device buffer (call gen_reset)");
+    gen_state chk;
+    if (gen_layout(st->n_envs, st->H, st->W, st->mode, &st->params, st->seed, &chk) != GEN_OK) return GEN_EINVAL;
+    if (chk.stride != st->stride || chk.bytes != st->bytes || chk.off_army != st->off_army ||
+        chk.n_players != st->n_players)
+        return fail(GEN_EINVAL, "state descriptor fields are inconsistent");
+    return GEN_OK;
+}
+
+gen::EnvArgs env_args(const gen_state &st)
+{
+    gen::EnvArgs a{};
+    a.g = geom_of(st);
+    a.prm = prm_of(st.params);
+    a.seed = st.seed;
+    a.env_base = st.env_base;
+    uint8_t *base = static_cast<uint8_t *>(st.d_buf);
+    a.sc = reinterpret_cast<gen::EnvScalars *>(base + st.off_scalars);
+    a.owner = reinterpret_cast<int8_t *>(base + st.off_owner);
+    a.type = base + st.off_type;
+    a.army = reinterpret_cast<int32_t *>(base + st.off_army);
+    return a;
+}
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
+{
+    if (d_obs == nullptr) return GEN_OK;
+    const uint64_t B = (uint64_t)st.n_players * 8 * st.H * st.W;
+    const uintptr_t need = (B % 16 == 0) ? 16 : 8;
+    if (!aligned(d_obs, need)) return fail(GEN_EINVAL, "d_obs must be %u-byte aligned", (unsigned)need);
+    return GEN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gen_version(void) { return GEN_LAYOUT_VERSION; }
+
+const char *gen_last_error(void) { return g_last_error.c_str(); }
+
+int gen_default_params(int32_t mode, int32_t n_players, gen_params *out)
+{
+    if (out == nullptr) return fail(GEN_EINVAL, "out is NULL");
+    const int P = players_of(mode, n_players);
+    if (P < 2 || P > GEN_MAX_PLAYERS) return fail(GEN_EINVAL, "mode %d with %d players is not a game", mode, n_players);
+    std::memset(out, 0, sizeof *out);
+    out->n_players = P;
+    out->mountain_thresh = 858993459u;  // floor(2^32 / 5): 20% mountains
+    out->cities_min = 9;
+    out->cities_max = 11;
+    out->city_army_min = 40;
+    out->city_army_max = 50;
+    out->min_general_dist = 9;
+    out->auto_reset = 1;
+    out->pregrow = 0;
+    return ok();
+}
+
+int gen_layout(int32_t n_envs, int32_t H, int32_t W, int32_t mode, const gen_params *params, uint64_t seed,
+               gen_state *out)
+{
+    if (out == nullptr) return fail(GEN_EINVAL, "out is NULL");
+    if (n_envs < 1) return fail(GEN_EINVAL, "n_envs %d must be positive", n_envs);
+    if (H < GEN_MIN_SIDE || H > GEN_MAX_SIDE || W < GEN_MIN_SIDE || W > GEN_MAX_SIDE)
+        return fail(GEN_EINVAL, "grid %dx%d outside %d..%d per side", H, W, GEN_MIN_SIDE, GEN_MAX_SIDE);
+    gen_params p;
+    if (params == nullptr) {
+        if (mode == GEN_FFA) return fail(GEN_EINVAL, "free-for-all needs params (n_players)");
+        if (gen_default_params(mode, 0, &p) != GEN_OK) return GEN_EINVAL;
+    } else {
+        p = *params;
+    }
+    const int P = players_of(mode, p.n_players);
+    if (P < 2 || P > GEN_MAX_PLAYERS)
+        return fail(GEN_EINVAL, "mode %d with %d players is not a game", mode, p.n_players);
+    p.n_players = P;
+    if (check_params(p, P, H * W) != GEN_OK) return GEN_EINVAL;
+
+    std::memset(out, 0, sizeof *out);
+    out->version = GEN_LAYOUT_VERSION;
+    out->n_envs = n_envs;
+    out->H = H;
+    out->W = W;
+    out->mode = mode;
+    out->n_players = P;
+    out->stride = (H * W + 15) & ~15;
+    out->seed = seed;
+    out->params = p;
+    const uint64_t E = (uint64_t)n_envs, S = (uint64_t)out->stride;
+    out->off_scalars = 0;
+    out->off_owner = align256(E * sizeof(gen::EnvScalars));
+    out->off_type = out->off_owner + align256(E * S);
+    out->off_army = out->off_type + align256(E * S);
+    out->bytes = out->off_army + align256(E * S * 4);
+    out->d_buf = nullptr;
+    return ok();
+}
+
+uint64_t gen_state_bytes(int32_t n_envs, int32_t H, int32_t W, int32_t mode, const gen_params *params)
+{
+    gen_state st;
+    if (gen_layout(n_envs, H, W, mode, params, 0, &st) != GEN_OK) return 0;
+    return st.bytes;
+}
+
+int gen_reset(uint64_t seed, uint64_t env_base, int32_t n_envs, int32_t H, int32_t W, int32_t mode,
+              const gen_params *params, void *d_buf, uint64_t buf_bytes, uint8_t *d_obs, void *stream, gen_state *out)
+{
+    gen_state st;
+    if (gen_layout(n_envs, H, W, mode, params, seed, &st) != GEN_OK) return GEN_EINVAL;
+    if (d_buf == nullptr || !aligned(d_buf, 256)) return fail(GEN_EINVAL, "d_buf must be a 256-byte aligned device pointer");
+    if (buf_bytes < st.bytes)
+        return fail(GEN_ENOMEM, "state buffer holds %llu bytes, layout needs %llu", (unsigned long long)buf_bytes,
+                    (unsigned long long)st.bytes);
+    st.env_base = env_base;
+    st.d_buf = d_buf;
+    if (check_obs_ptr(st, d_obs) != GEN_OK) return GEN_EINVAL;
+    gen::EnvArgs a = env_args(st);
+    a.obs = d_obs;
+    hipError_t e = gen::launch_reset(a, n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "reset launch");
+    if (out) *out = st;
+    return ok();
+}
+
+int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int32_t *d_rewards, uint8_t *d_dones,
+             int32_t *d_land, int64_t *d_army, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (d_actions == nullptr || d_rewards == nullptr || d_dones == nullptr)
+        return fail(GEN_EINVAL, "d_actions, d_rewards and d_dones are required");
+    if ((d_land == nullptr) != (d_army == nullptr)) return fail(GEN_EINVAL, "d_land and d_army go together");
+    if (check_obs_ptr(*st, d_obs) != GEN_OK) return GEN_EINVAL;
+    if (!aligned(d_actions, 4) || !aligned(d_rewards, 4) || (d_army && !aligned(d_army, 8)) ||
+        (d_land && !aligned(d_land, 4)))
+        return fail(GEN_EINVAL, "misaligned action, reward or scoreboard pointer");
+    gen::EnvArgs a = env_args(*st);
+    a.actions = d_actions;
+    a.obs = d_obs;
+    a.rewards = d_rewards;
+    a.dones = d_dones;
+    a.land = d_land;
+    a.army_tot = d_army;
+    hipError_t e = gen::launch_step(a, st->n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return ok();
+}
+
+int gen_sample_actions(const gen_state *st, uint64_t actor_seed, uint64_t step_idx, int32_t *d_actions, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (d_actions == nullptr || !aligned(d_actions, 4)) return fail(GEN_EINVAL, "d_actions must be an aligned device pointer");
+    const gen::EnvArgs ea = env_args(*st);
+    gen::SampleArgs a{};
+    a.g = ea.g;
+    a.env_base = st->env_base;
+    a.actor_seed = actor_seed;
+    a.step_idx = step_idx;
+    a.sc = ea.sc;
+    a.owner = ea.owner;
+    a.type = ea.type;
+    a.army = ea.army;
+    a.actions = d_actions;
+    hipError_t e = gen::launch_sample(a, st->n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "sample launch");
+    return ok();
+}
+
+int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (d_obs == nullptr) return fail(GEN_EINVAL, "d_obs is NULL");
+    if (check_obs_ptr(*st, d_obs) != GEN_OK) return GEN_EINVAL;
+    gen::EnvArgs a = env_args(*st);
+    a.obs = d_obs;
+    hipError_t e = gen::launch_observe(a, st->n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "observe launch");
+    return ok();
+}
+
+int gen_get_state(const gen_state *st, gen_host_state *h, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    std::vector<uint8_t> buf(st->bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(buf.data(), st->d_buf, st->bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "state download");
+    const int HW = st->H * st->W, S = st->stride, P = st->n_players;
+    const gen::EnvScalars *sc = reinterpret_cast<const gen::EnvScalars *>(buf.data() + st->off_scalars);
+    for (int64_t i = 0; i < st->n_envs; ++i) {
+        std::memcpy(h->owner + i * HW, buf.data() + st->off_owner + i * S, HW);
+        std::memcpy(h->type + i * HW, buf.data() + st->off_type + i * S, HW);
+        std::memcpy(h->army + i * HW, buf.data() + st->off_army + i * S * 4, (size_t)HW * 4);
+        h->turn[i] = sc[i].turn;
+        h->episode[i] = sc[i].episode;
+        h->alive[i] = sc[i].alive;
+        h->finished[i] = sc[i].finished;
+        for (int p = 0; p < P; ++p) h->gpos[i * P + p] = sc[i].gpos[p];
+    }
+    return ok();
+}
+
+int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    if (n_ids < 0 || (n_ids > 0 && h_env_ids == nullptr)) return fail(GEN_EINVAL, "bad env id list");
+    for (int32_t i = 0; i < n_ids; ++i)
+        if (h_env_ids[i] < 0 || h_env_ids[i] >= st->n_envs)
+            return fail(GEN_EINVAL, "env id %d outside [0, %d)", h_env_ids[i], st->n_envs);
+    const int HW = st->H * st->W, S = st->stride, P = st->n_players;
+    const uint8_t *base = static_cast<const uint8_t *>(st->d_buf);
+    std::vector<gen::EnvScalars> sc((size_t)n_ids);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    for (int32_t i = 0; i < n_ids && e == hipSuccess; ++i) {
+        const uint64_t id = (uint64_t)h_env_ids[i];
+        e = hipMemcpyAsync(h->owner + (size_t)i * HW, base + st->off_owner + id * S, HW, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->type + (size_t)i * HW, base + st->off_type + id * S, HW, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->army + (size_t)i * HW, base + st->off_army + id * S * 4, (size_t)HW * 4,
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&sc[i], base + st->off_scalars + id * sizeof(gen::EnvScalars),
+                               sizeof(gen::EnvScalars), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "env download");
+    for (int32_t i = 0; i < n_ids; ++i) {
+        h->turn[i] = sc[i].turn;
+        h->episode[i] = sc[i].episode;
+        h->alive[i] = sc[i].alive;
+        h->finished[i] = sc[i].finished;
+        for (int p = 0; p < P; ++p) h->gpos[(size_t)i * P + p] = sc[i].gpos[p];
+    }
+    return ok();
+}
+
+int gen_set_state(const gen_state *st, const gen_host_state *h, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    const int HW = st->H * st->W, S = st->stride, P = st->n_players;
+    for (int64_t i = 0; i < st->n_envs; ++i) {
+        for (int c = 0; c < HW; ++c) {
+            const int o = h->owner[i * HW + c], t = h->type[i * HW + c];
+            if (o < -1 || o >= P) return fail(GEN_EINVAL, "env %lld cell %d: owner %d outside [-1, %d)", (long long)i, c, o, P);
+            if (t > GEN_GENERAL) return fail(GEN_EINVAL, "env %lld cell %d: type %d outside [0, 3]", (long long)i, c, t);
+            if (h->army[i * HW + c] < 0) return fail(GEN_EINVAL, "env %lld cell %d: negative army", (long long)i, c);
+        }
+        for (int p = 0; p < P; ++p) {
+            const int g = h->gpos[i * P + p];
+            if (g < 0 || g >= HW) return fail(GEN_EINVAL, "env %lld: general %d at cell %d outside the grid", (long long)i, p, g);
+        }
+        if (h->alive[i] >> P) return fail(GEN_EINVAL, "env %lld: alive mask has bits beyond %d players", (long long)i, P);
+        if (h->turn[i] < 0) return fail(GEN_EINVAL, "env %lld: negative turn", (long long)i);
+        if (h->finished[i] > 1) return fail(GEN_EINVAL, "env %lld: finished must be 0 or 1", (long long)i);
+    }
+    std::vector<uint8_t> buf(st->bytes, 0);
+    gen::EnvScalars *sc = reinterpret_cast<gen::EnvScalars *>(buf.data() + st->off_scalars);
+    for (int64_t i = 0; i < st->n_envs; ++i) {
+        int8_t *ow = reinterpret_cast<int8_t *>(buf.data() + st->off_owner + i * S);
+        std::memset(ow, 0xFF, S);   // padding cells: neutral
+        std::memcpy(ow, h->owner + i * HW, HW);
+        std::memcpy(buf.data() + st->off_type + i * S, h->type + i * HW, HW);
+        std::memcpy(buf.data() + st->off_army + i * S * 4, h->army + i * HW, (size_t)HW * 4);
+        sc[i].turn = h->turn[i];
+        sc[i].episode = h->episode[i];
+        sc[i].alive = h->alive[i];
+        sc[i].finished = h->finished[i];
+        for (int p = 0; p < gen::kMaxP; ++p) sc[i].gpos[p] = (int16_t)(p < P ? h->gpos[i * P + p] : -1);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(st->d_buf, buf.data(), st->bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "state upload");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// device.hpp -- gfx950 device helpers for the batched Generals.io step:
+// Philox4x64-10, wave64 primitives, SWAR byte tests, per-launch geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gen {
+
+constexpr int kWave = 64;
+constexpr int kMaxP = 8;
+constexpr int kMaxCells = 1024;
+constexpr int kMaxWords = 16;            // 64-bit words of a per-cell bitmap
+
+enum : int { PLAIN = 0, MOUNTAIN = 1, CASTLE = 2, GENERAL = 3 };
+enum : int { MODE_1V1 = 0, MODE_2V2 = 1, MODE_FFA = 2 };
+enum : uint32_t { DOM_MAPGEN = 1, DOM_ACTIONS = 2, DOM_PREGROW = 3 };
+
+// 32-byte per-env record of the device layout (documented in generals.h).
+struct __align__(16) EnvScalars {
+    int32_t turn;
+    uint32_t episode;
+    uint8_t alive;
+    uint8_t finished;
+    uint8_t pad[6];
+    int16_t gpos[8];
+};
+static_assert(sizeof(EnvScalars) == 32, "scalar record is 32 bytes");
+
+// Geometry of one launch (all envs the same shape).
+struct Geom {
+    int H, W, HW, S, P, mode, NW;
+    uint32_t magic_w;    // ceil(2^20 / W): c / W == (c * magic_w) >> 20 for c < 1024
+    uint32_t magic_hw;   // ceil(2^32 / HW): b / HW == (b * magic_hw) >> 32 for b < 65536
+};
+
+struct GenParamsDev {
+    uint32_t thresh;
+    int cmin, cmax, amin, amax, dmin, auto_reset, pregrow;
+};
+
+// ---------------------------------------------------------------- wave ops
+// Make LDS writes of one lane visible to the other lanes of the same wave and
+// keep the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Value of `v` held by lane `src` (any lane index; taken mod 64).
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)v);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    uint32_t lo = shfl32((uint32_t)v, src), hi = shfl32((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Broadcast of a wave-uniform lane's value.
+__device__ __forceinline__ int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ int readfirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v += shfl32(v, lane_id() ^ d);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    for (int d = 32; d >= 1; d >>= 1) v += (int64_t)shfl64((uint64_t)v, lane_id() ^ d);
+    return v;
+}
+
+// Inclusive prefix sum over the wave (lane order).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = lane_id();
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = shfl32(v, lane - d);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- Philox4x64-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): ten rounds of two 64x64->128 multiplies; the key advances by the
+// two Weyl constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64_t &x2, uint64_t &x3,
+                                              uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
+        const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
+        const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+// 32-bit draw j of the stream keyed (seed, dom) with counter prefix (c0, c1, c2):
+// block j/8 is counter word 3; 64-bit word (j/2)%4; low half first.
+__device__ __forceinline__ uint32_t draw32(uint64_t seed, uint32_t dom, uint64_t c0, uint64_t c1, uint64_t c2,
+                                           uint32_t j)
+{
+    uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = j >> 3;
+    philox4x64_10(x0, x1, x2, x3, seed, dom);
+    const uint32_t w = (j >> 1) & 3;
+    const uint64_t v = w == 0 ? x0 : w == 1 ? x1 : w == 2 ? x2 : x3;
+    return (j & 1) ? (uint32_t)(v >> 32) : (uint32_t)v;
+}
+
+// Uniform pick in [0, n): floor(r * n / 2^32).
+__device__ __forceinline__ uint32_t pick(uint32_t r, uint32_t n) { return (uint32_t)(((uint64_t)r * n) >> 32); }
+
+// ---------------------------------------------------------------- SWAR bytes
+// 0x01 in every byte of x equal to the byte b, else 0x00 (exact, no carries
+// across bytes).
+__device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t b)
+{
+    const uint32_t d = x ^ (b * 0x01010101u);
+    const uint32_t t = ((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d;
+    return (~t >> 7) & 0x01010101u;
+}
+
+// Bits 0..3 of v to 0x01 in bytes 0..3.
+__device__ __forceinline__ uint32_t spread4(uint32_t v) { return (v * 0x00204081u) & 0x01010101u; }
+
+__device__ __forceinline__ int32_t sat_inc(int32_t a) { return a + (a != INT32_MAX ? 1 : 0); }
+
+__device__ __forceinline__ int32_t sat_add(int32_t a, int32_t b)
+{
+    const int64_t s = (int64_t)a + (int64_t)b;
+    return s > INT32_MAX ? INT32_MAX : (int32_t)s;
+}
+
+__device__ __forceinline__ int div_w(int c, const Geom &g) { return (int)(((uint32_t)c * g.magic_w) >> 20); }
+__device__ __forceinline__ uint32_t div_hw(uint32_t b, const Geom &g)
+{
+    return (uint32_t)(((uint64_t)b * g.magic_hw) >> 32);
+}
+
+// Bit positions b of word w (cell 64w + b) that lie in column 0 / column W-1,
+// and the positions that are real cells (< HW).
+struct ColMasks { uint64_t col0, colL, valid; };
+
+__device__ __forceinline__ ColMasks col_masks(int w, const Geom &g)
+{
+    ColMasks m{0, 0, 0};
+    const int r0 = (64 * w) % g.W;
+    for (int b = (g.W - r0) % g.W; b < 64; b += g.W) m.col0 |= 1ull << b;
+    for (int b = (2 * g.W - 1 - r0) % g.W; b < 64; b += g.W) m.colL |= 1ull << b;
+    const int left = g.HW - 64 * w;
+    m.valid = left >= 64 ? ~0ull : left <= 0 ? 0ull : ((1ull << left) - 1);
+    return m;
+}
+
+// Position of the idx-th set bit (idx < popcount) of a bitmap of nw words.
+__device__ __forceinline__ int bm_select(const uint64_t *bm, int nw, uint32_t idx)
+{
+    for (int w = 0; w < nw; ++w) {
+        uint64_t x = bm[w];
+        const uint32_t pc = (uint32_t)__popcll(x);
+        if (idx < pc) {
+            int base = 0;
+            for (int width = 32; width >= 1; width >>= 1) {
+                const uint32_t c = (uint32_t)__popcll(x & ((1ull << width) - 1));
+                if (idx >= c) { idx -= c; x >>= width; base += width; }
+            }
+            return w * 64 + base;
+        }
+        idx -= pc;
+    }
+    return -1;
+}
+
+}  // namespace gen

@@ -1,0 +1,690 @@
+// kernels.hip -- gfx950 kernels of the batched Generals.io environment step
+// (arxiv 2606.23348, Section IV).  One wave64 owns one environment: the grid
+// (owner int8, type uint8, army int32) is loaded from HBM into LDS once, the
+// whole step runs on it, and owner/army plus the uint8 observation stream
+// back out with 16-byte stores.  No MFMA: nothing here is a contraction.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace gen {
+
+// ---------------------------------------------------------------- LDS carve-up
+// Per env, S = padded cells per row (multiple of 16):
+//   army  int32 [S] | owner int8 [S] | type uint8 [S] | armyc uint8 [S] + 16
+//   code  uint8 [P*S] + 16            (per player, bits = obs channels 0..6)
+//   tbm   u64 [P][16]                 (team-owned cell bitmaps)
+//   vis   u64 [P][16]                 (visible cell bitmaps)
+//   gbm   u64 [3][16] + int32 [8]      (map generator scratch bitmaps, general cells)
+struct Lds {
+    int32_t *army;
+    int8_t *owner;
+    uint8_t *type;
+    uint8_t *armyc;
+    uint8_t *code;
+    uint64_t *tbm, *vis, *gbm;
+};
+
+__host__ __device__ inline uint32_t lds_bytes_for(int S, int P)
+{
+    return (uint32_t)(4 * S + S + S + (S + 16) + (P * S + 16) + 8 * 16 * (2 * P + 3) + 32);
+}
+
+__device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
+{
+    Lds L;
+    uint32_t o = 0;
+    L.army = reinterpret_cast<int32_t *>(smem + o); o += 4 * g.S;
+    L.owner = reinterpret_cast<int8_t *>(smem + o); o += g.S;
+    L.type = smem + o; o += g.S;
+    L.armyc = smem + o; o += g.S + 16;
+    L.code = smem + o; o += g.P * g.S + 16;
+    L.tbm = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
+    L.vis = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
+    L.gbm = reinterpret_cast<uint64_t *>(smem + o);
+    return L;
+}
+
+// ---------------------------------------------------------------- map generation
+// Section IV-A generator family (reading R14).  Executed by the whole wave
+// with uniform control flow; every random choice is a Philox draw indexed
+// exactly as the generator's draw order defines.  Leaves the grid in LDS and
+// the scalars in `s`.
+__device__ void mapgen_wave(const Lds &L, const Geom &g, const GenParamsDev &prm, uint64_t seed, uint64_t env_id,
+                            uint32_t episode, EnvScalars &s)
+{
+    const int lane = lane_id();
+    const int HW = g.HW, W = g.W, NW = g.NW;
+    uint64_t *pass = L.gbm, *comp = L.gbm + 16, *cand = L.gbm + 32;
+    int *gp = reinterpret_cast<int *>(L.gbm + 48);   // general cells, written by lane 0
+    bool placed = false;
+
+    for (int attempt = 0; attempt < 128 && !placed; ++attempt) {
+        const uint32_t T = attempt < 64 ? prm.thresh : 0u;
+        // G1: one draw per cell; a Philox block gives the draws of 8 cells.
+        for (int b = lane; b * 8 < g.S; b += kWave) {
+            uint64_t x0 = env_id, x1 = episode, x2 = (uint64_t)attempt, x3 = (uint64_t)b;
+            philox4x64_10(x0, x1, x2, x3, seed, DOM_MAPGEN);
+            const uint64_t w4[4] = {x0, x1, x2, x3};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = b * 8 + t;
+                const uint32_t r = (t & 1) ? (uint32_t)(w4[t >> 1] >> 32) : (uint32_t)w4[t >> 1];
+                if (c < g.S) {
+                    L.type[c] = (c < HW && r < T) ? MOUNTAIN : PLAIN;
+                    L.owner[c] = -1;
+                    L.army[c] = 0;
+                }
+            }
+        }
+        wave_sync();
+        // passable bitmap and its population
+        uint32_t K = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int c = w * 64 + lane;
+            const uint64_t m = ballot(c < HW && L.type[c] != MOUNTAIN);
+            if (lane == 0) pass[w] = m;
+            K += (uint32_t)__popcll(m);
+        }
+        wave_sync();
+        if (K == 0) continue;
+        uint32_t j = (uint32_t)HW;
+        // G2: first general over the non-mountain cells in row-major order
+        const int g0 = bm_select(pass, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), K));
+        if (lane == 0) { gp[0] = g0; L.type[g0] = GENERAL; }
+        // G3: 4-connected component of gp[0] (bitmap flood fill to a fixpoint)
+        {
+            const ColMasks cm = col_masks(lane < NW ? lane : 0, g);
+            const uint64_t pw = lane < NW ? pass[lane] : 0ull;
+            uint64_t cw = (lane == (g0 >> 6)) ? (1ull << (g0 & 63)) : 0ull;
+            for (;;) {
+                const uint64_t prev = shfl64(cw, lane - 1), next = shfl64(cw, lane + 1);
+                const uint64_t pv = lane > 0 ? prev : 0ull, nx = lane < NW - 1 ? next : 0ull;
+                uint64_t n = cw;
+                n |= ((cw << 1) | (pv >> 63)) & ~cm.col0;
+                n |= ((cw >> 1) | (nx << 63)) & ~cm.colL;
+                n |= (cw << W) | (pv >> (64 - W));
+                n |= (cw >> W) | (nx << (64 - W));
+                n &= pw;
+                const bool changed = ballot(n != cw) != 0ull;
+                cw = n;
+                if (!changed) break;
+            }
+            if (lane < NW) comp[lane] = cw;
+        }
+        wave_sync();
+        // G4: each further general in the component, far enough from all earlier ones
+        bool ok = true;
+        for (int i = 1; i < g.P; ++i) {
+            uint32_t n = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int c = w * 64 + lane;
+                bool in = c < HW && ((comp[w] >> lane) & 1ull) && L.type[c] != GENERAL;
+                if (in) {
+                    const int r = div_w(c, g), col = c - r * W;
+                    for (int k = 0; k < i; ++k) {
+                        const int gr = div_w(gp[k], g), gc = gp[k] - gr * W;
+                        const int d = abs(r - gr) + abs(col - gc);
+                        if (d < prm.dmin) in = false;
+                    }
+                }
+                const uint64_t m = ballot(in);
+                if (lane == 0) cand[w] = m;
+                n += (uint32_t)__popcll(m);
+            }
+            wave_sync();
+            if (n == 0) { ok = false; break; }
+            const int gi = bm_select(cand, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), n));
+            if (lane == 0) { gp[i] = gi; L.type[gi] = GENERAL; }
+            wave_sync();
+        }
+        if (!ok) continue;
+        // G5: cities on remaining plain cells anywhere
+        const int ncity = prm.cmin + (int)pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++),
+                                               (uint32_t)(prm.cmax - prm.cmin + 1));
+        for (int t = 0; t < ncity; ++t) {
+            uint32_t n = 0;
+            for (int w = 0; w < NW; ++w) {
+                const int c = w * 64 + lane;
+                const uint64_t m = ballot(c < HW && L.type[c] == PLAIN);
+                if (lane == 0) cand[w] = m;
+                n += (uint32_t)__popcll(m);
+            }
+            wave_sync();
+            if (n == 0) break;
+            const int c = bm_select(cand, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), n));
+            const int32_t a = prm.amin + (int32_t)pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++),
+                                                       (uint32_t)(prm.amax - prm.amin + 1));
+            if (lane == 0) { L.type[c] = CASTLE; L.army[c] = a; }
+            wave_sync();
+        }
+        placed = true;
+    }
+    if (!placed) {
+        // deterministic last resort: no mountains, no cities, fixed border cells
+        for (int c = lane; c < g.S; c += kWave) { L.type[c] = PLAIN; L.owner[c] = -1; L.army[c] = 0; }
+        if (lane == 0) {
+            for (int i = 0; i < g.P; ++i) {
+                const int r = (i == 0 || i == 2 || i == 4) ? 0 : (i == 1 || i == 3 || i == 5) ? g.H - 1 : g.H / 2;
+                const int c = (i == 0 || i == 3 || i == 6) ? 0 : (i == 1 || i == 2 || i == 7) ? W - 1 : W / 2;
+                gp[i] = r * W + c;
+            }
+        }
+    }
+    wave_sync();
+    // G6: generals (plus pre-grown armies on the overflow-stress workload)
+    if (lane == 0) {
+        for (int i = 0; i < g.P; ++i) {
+            const int c = gp[i];
+            L.type[c] = GENERAL;
+            L.owner[c] = (int8_t)i;
+            int32_t a = 1;
+            if (prm.pregrow && episode == 0 && (env_id & 3) == 0)
+                a = 100000 + (int32_t)pick(draw32(seed, DOM_PREGROW, env_id, 0, 0, (uint32_t)i), 900001u);
+            L.army[c] = a;
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < kMaxP; ++i) s.gpos[i] = (int16_t)(i < g.P ? gp[i] : -1);
+    s.turn = 0;
+    s.episode = episode;
+    s.alive = (uint8_t)((1u << g.P) - 1u);
+    s.finished = 0;
+    wave_sync();
+}
+
+// ---------------------------------------------------------------- moves (Section IV-D)
+__device__ __forceinline__ bool is_ally(int mode, int a, int b) { return mode == MODE_2V2 && a != b && ((a ^ b) & 1) == 0; }
+
+// Apply player i's action on lane 0.  Returns the player whose general was
+// captured (-1 if none); the captured general becomes a castle here.
+__device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int i, int32_t a)
+{
+    if (!((s.alive >> i) & 1)) return -1;
+    if (a < 0 || a >= g.HW * 9) return -1;
+    const int src = a / 9, k = a - src * 9;
+    if (k == 0) return -1;
+    const int dir = (k - 1) & 3;
+    const bool half = k >= 5;
+    int r = div_w(src, g), c = src - r * g.W;
+    r += dir == 0 ? -1 : dir == 1 ? 1 : 0;
+    c += dir == 2 ? -1 : dir == 3 ? 1 : 0;
+    if (r < 0 || r >= g.H || c < 0 || c >= g.W) return -1;
+    const int dst = r * g.W + c;
+    if (L.type[dst] == MOUNTAIN || L.owner[src] != i) return -1;
+    const int32_t have = L.army[src];
+    if (have <= 1) return -1;
+    const int32_t m = half ? (have >> 1) : have - 1;
+    L.army[src] = have - m;
+    const int o = L.owner[dst];
+    const int32_t d = L.army[dst];
+    if (o == i) {
+        L.army[dst] = sat_add(d, m);
+    } else if (o >= 0 && is_ally(g.mode, o, i)) {
+        L.army[dst] = sat_add(d, m);
+        L.owner[dst] = (int8_t)i;
+    } else if (m > d) {
+        L.owner[dst] = (int8_t)i;
+        L.army[dst] = m - d;
+        if (L.type[dst] == GENERAL) {
+            int victim = -1;
+#pragma unroll
+            for (int v = 0; v < kMaxP; ++v) {
+                if (v < g.P && victim < 0 && s.gpos[v] == dst && ((s.alive >> v) & 1) && v != i &&
+                    !is_ally(g.mode, v, i))
+                    victim = v;
+            }
+            if (victim >= 0) L.type[dst] = CASTLE;
+            return victim;
+        }
+    } else {
+        L.army[dst] = d - m;
+    }
+    return -1;
+}
+
+// All players' moves in rotating priority (reading R5), captures applied at
+// once by the whole wave (Section IV-E transfer, reading R9 halving).
+__device__ void resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_t my_action)
+{
+    const int lane = lane_id();
+    for (int j = 0; j < g.P; ++j) {
+        const int i = (s.turn + j) % g.P;
+        const int32_t a = readlane(my_action, i);
+        int victim = -1;
+        if (lane == 0) victim = apply_move(L, g, s, i, a);
+        victim = readfirst(victim);
+        wave_sync();
+        if (victim >= 0) {
+            for (int c = lane; c < g.HW; c += kWave) {
+                if (L.owner[c] == victim) {
+                    L.owner[c] = (int8_t)i;
+                    L.army[c] = L.army[c] >> 1;
+                }
+            }
+            s.alive = (uint8_t)(s.alive & ~(1u << victim));
+            wave_sync();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fused env kernel
+enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
+enum { OBS_A16 = 0, OBS_A4 = 1, OBS_A1C16 = 2, OBS_A1C8 = 3 };
+
+__device__ __forceinline__ uint32_t vismask(uint32_t code4)
+{
+    return (((code4 >> 6) & 0x01010101u) ^ 0x01010101u) * 0xFFu;
+}
+
+// One obs byte (slow path for dwords that straddle two planes).
+__device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32_t b)
+{
+    const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
+    const uint32_t cd = L.code[p * g.S + c];
+    return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
+}
+
+// Four consecutive obs bytes at byte offset b (b % 4 == 0) of an env block.
+template <int OBSV>
+__device__ __forceinline__ uint32_t obs_dword(const Lds &L, const Geom &g, uint32_t b)
+{
+    const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
+    if (OBSV == OBS_A4) {
+        const uint32_t cd = *reinterpret_cast<const uint32_t *>(L.code + p * g.S + c);
+        if (ch < 7) return (cd >> ch) & 0x01010101u;
+        return *reinterpret_cast<const uint32_t *>(L.armyc + c) & vismask(cd);
+    } else {
+        if (c + 3 >= (uint32_t)g.HW) {
+            return obs_byte(L, g, b) | (obs_byte(L, g, b + 1) << 8) | (obs_byte(L, g, b + 2) << 16) |
+                   (obs_byte(L, g, b + 3) << 24);
+        }
+        const uint32_t o = p * g.S + c;
+        const uint32_t *cw = reinterpret_cast<const uint32_t *>(L.code);
+        const uint32_t cd = __builtin_amdgcn_alignbyte(cw[(o >> 2) + 1], cw[o >> 2], o & 3);
+        if (ch < 7) return (cd >> ch) & 0x01010101u;
+        const uint32_t *aw = reinterpret_cast<const uint32_t *>(L.armyc);
+        const uint32_t ac = __builtin_amdgcn_alignbyte(aw[(c >> 2) + 1], aw[c >> 2], c & 3);
+        return ac & vismask(cd);
+    }
+}
+
+template <int KIND, int OBSV, bool SB>
+__global__ __launch_bounds__(64) void k_env(EnvArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = lane_id();
+    const int e = blockIdx.x;
+    const Geom g = a.g;
+    const Lds L = carve(smem, g);
+    const uint64_t env_id = a.env_base + (uint64_t)e;
+    const size_t cell0 = (size_t)e * g.S;
+
+    EnvScalars s;
+    bool write_type = false, grow2 = false, grow50 = false, done = false;
+    uint32_t win = 0, lose = 0;
+
+    if (KIND == K_RESET) {
+        mapgen_wave(L, g, a.prm, a.seed, env_id, 0u, s);
+        write_type = true;
+    } else {
+        s = a.sc[e];
+        // state HBM -> LDS, 16-byte loads
+        const int n16 = g.S >> 4;
+        const uint4 *go = reinterpret_cast<const uint4 *>(a.owner + cell0);
+        const uint4 *gt = reinterpret_cast<const uint4 *>(a.type + cell0);
+        const uint4 *ga = reinterpret_cast<const uint4 *>(a.army + cell0);
+        for (int i = lane; i < n16; i += kWave) {
+            reinterpret_cast<uint4 *>(L.owner)[i] = go[i];
+            reinterpret_cast<uint4 *>(L.type)[i] = gt[i];
+        }
+        for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(L.army)[i] = ga[i];
+        int32_t act = 0;
+        if (KIND == K_STEP && lane < g.P) act = a.actions[(size_t)e * g.P + lane];
+        wave_sync();
+        if (KIND == K_STEP) {
+            if (!s.finished) {
+                const uint32_t alive0 = s.alive;
+                resolve_moves(L, g, s, act);
+                s.turn += 1;
+                grow2 = (s.turn & 1) == 0;
+                grow50 = (s.turn % 50) == 0;
+                // terminal and rewards (Section III, Section IV-E; reading R11)
+                const uint32_t alive = s.alive;
+                if (g.mode == MODE_2V2) {
+                    const bool t0 = (alive & 0x5u) != 0, t1 = (alive & 0xAu) != 0;
+                    if (!t0 || !t1) {
+                        done = true;
+                        const uint32_t winners = t0 ? 0x5u : 0xAu;
+                        win = winners;
+                        lose = 0xFu & ~winners;
+                    }
+                } else {
+                    lose = alive0 & ~alive;
+                    if (__popc(alive) == 1) { done = true; win = alive; }
+                }
+                if (done) {
+                    if (a.prm.auto_reset) {
+                        mapgen_wave(L, g, a.prm, a.seed, env_id, s.episode + 1u, s);
+                        write_type = true;
+                        grow2 = grow50 = false;
+                    } else {
+                        s.finished = 1;
+                    }
+                }
+            } else {
+                done = true;
+            }
+        }
+    }
+
+    // ---- growth (Section IV-C), state store, army clamp, scoreboard
+    const bool grow = grow2 || grow50;
+    int land_acc[kMaxP];
+    int64_t army_acc[kMaxP];
+    if (SB) {
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p) { land_acc[p] = 0; army_acc[p] = 0; }
+    }
+    {
+        const int nq = g.S >> 2;
+        uint32_t *go = reinterpret_cast<uint32_t *>(a.owner + cell0);
+        uint32_t *gt = reinterpret_cast<uint32_t *>(a.type + cell0);
+        int4 *ga = reinterpret_cast<int4 *>(a.army + cell0);
+        for (int q = lane; q < nq; q += kWave) {
+            const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
+            const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
+            int4 a4 = reinterpret_cast<const int4 *>(L.army)[q];
+            int32_t av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int o = (int8_t)(o4 >> (8 * k));
+                const uint32_t t = (t4 >> (8 * k)) & 0xFFu;
+                if (grow && o >= 0 && ((grow2 && t >= (uint32_t)CASTLE) || (grow50 && t == (uint32_t)PLAIN)))
+                    av[k] = sat_inc(av[k]);
+                if (SB) {
+#pragma unroll
+                    for (int p = 0; p < kMaxP; ++p) {
+                        if (o == p) { land_acc[p] += 1; army_acc[p] += av[k]; }
+                    }
+                }
+            }
+            if (KIND != K_OBSERVE) {
+                ga[q] = make_int4(av[0], av[1], av[2], av[3]);
+                go[q] = o4;
+                if (write_type) gt[q] = t4;
+            }
+            uint32_t ac = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ac |= (uint32_t)(av[k] > 255 ? 255 : av[k]) << (8 * k);
+            reinterpret_cast<uint32_t *>(L.armyc)[q] = ac;
+        }
+    }
+    if (SB) {
+        for (int p = 0; p < g.P; ++p) {
+            int lp = 0;
+            int64_t ap = 0;
+#pragma unroll
+            for (int t = 0; t < kMaxP; ++t) if (t == p) { lp = land_acc[t]; ap = army_acc[t]; }
+            lp = (int)wave_sum_u32((uint32_t)lp);
+            ap = wave_sum_i64(ap);
+            if (lane == 0) {
+                a.land[(size_t)e * g.P + p] = lp;
+                a.army_tot[(size_t)e * g.P + p] = ap;
+            }
+        }
+    }
+
+    // ---- per-player team bitmaps (ballot per 64 cells)
+    for (int w = 0; w < g.NW; ++w) {
+        const int c = w * 64 + lane;
+        const int o = c < g.HW ? (int)L.owner[c] : -1;
+        for (int p = 0; p < g.P; ++p) {
+            const bool in = (o == p) || (g.mode == MODE_2V2 && o == (p ^ 2));
+            const uint64_t m = ballot(in);
+            if (lane == 0) L.tbm[p * 16 + w] = m;
+        }
+    }
+    wave_sync();
+
+    // ---- fog (Section IV-B): 8-neighbour dilation = horizontal 3 then vertical 3
+    {
+        const int ppr = kWave / g.NW;                 // players per round
+        const int lp = lane / g.NW, w = lane - lp * g.NW;
+        const ColMasks cm = col_masks(w, g);
+        for (int p0 = 0; p0 < g.P; p0 += ppr) {
+            const int p = p0 + lp;
+            const bool valid = lp < ppr && p < g.P;
+            const uint64_t m = valid ? L.tbm[p * 16 + w] : 0ull;
+            uint64_t mp = shfl64(m, lane - 1), mn = shfl64(m, lane + 1);
+            if (w == 0) mp = 0ull;
+            if (w == g.NW - 1) mn = 0ull;
+            const uint64_t h = m | (((m << 1) | (mp >> 63)) & ~cm.col0) | (((m >> 1) | (mn << 63)) & ~cm.colL);
+            uint64_t hp = shfl64(h, lane - 1), hn = shfl64(h, lane + 1);
+            if (w == 0) hp = 0ull;
+            if (w == g.NW - 1) hn = 0ull;
+            const uint64_t v = (h | (h << g.W) | (hp >> (64 - g.W)) | (h >> g.W) | (hn << (64 - g.W))) & cm.valid;
+            if (valid) L.vis[p * 16 + w] = v;
+        }
+    }
+    wave_sync();
+
+    // ---- per-(player, cell) code byte: bit k = obs channel k for k < 7 (reading R16)
+    {
+        const int nq = (g.HW + 3) >> 2;
+        for (int p = 0; p < g.P; ++p) {
+            const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
+            uint32_t *cw = reinterpret_cast<uint32_t *>(L.code + p * g.S);
+            for (int q = lane; q < nq; q += kWave) {
+                const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
+                const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
+                const uint32_t vb = (uint32_t)(L.vis[p * 16 + (q >> 4)] >> ((q & 15) * 4)) & 0xFu;
+                const uint32_t visb = spread4(vb);
+                const uint32_t eqp = bytes_eq(o4, (uint32_t)p), eqa = bytes_eq(o4, ally);
+                const uint32_t neutral = (o4 >> 7) & 0x01010101u;
+                const uint32_t enemy = (neutral ^ 0x01010101u) & ~eqp & ~eqa;
+                const uint32_t mtn = t4 & ~(t4 >> 1) & 0x01010101u;
+                const uint32_t cas = (t4 >> 1) & ~t4 & 0x01010101u;
+                const uint32_t gen = t4 & (t4 >> 1) & 0x01010101u;
+                cw[q] = eqp | ((enemy & visb) << 1) | ((neutral & ~mtn & visb) << 2) | ((mtn & visb) << 3) |
+                        ((cas & visb) << 4) | ((gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
+            }
+        }
+    }
+    wave_sync();
+
+    // ---- observation stream: uint8 [P][8][H][W] per env, 16- or 8-byte stores
+    if (a.obs != nullptr) {
+        const uint32_t B = (uint32_t)(g.P * 8 * g.HW);
+        uint8_t *ob = a.obs + (size_t)e * B;
+        if (OBSV == OBS_A16) {
+            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
+                const uint32_t b = k << 4;
+                const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
+                const uint4 cd = *reinterpret_cast<const uint4 *>(L.code + p * g.S + c);
+                uint4 out;
+                if (ch < 7) {
+                    out.x = (cd.x >> ch) & 0x01010101u;
+                    out.y = (cd.y >> ch) & 0x01010101u;
+                    out.z = (cd.z >> ch) & 0x01010101u;
+                    out.w = (cd.w >> ch) & 0x01010101u;
+                } else {
+                    const uint4 ac = *reinterpret_cast<const uint4 *>(L.armyc + c);
+                    out.x = ac.x & vismask(cd.x);
+                    out.y = ac.y & vismask(cd.y);
+                    out.z = ac.z & vismask(cd.z);
+                    out.w = ac.w & vismask(cd.w);
+                }
+                *reinterpret_cast<uint4 *>(ob + b) = out;
+            }
+        } else if (OBSV == OBS_A4 || OBSV == OBS_A1C16) {
+            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
+                const uint32_t b = k << 4;
+                uint4 out;
+                out.x = obs_dword<OBSV>(L, g, b);
+                out.y = obs_dword<OBSV>(L, g, b + 4);
+                out.z = obs_dword<OBSV>(L, g, b + 8);
+                out.w = obs_dword<OBSV>(L, g, b + 12);
+                *reinterpret_cast<uint4 *>(ob + b) = out;
+            }
+        } else {
+            for (uint32_t k = lane; k < (B >> 3); k += kWave) {
+                const uint32_t b = k << 3;
+                uint2 out;
+                out.x = obs_dword<OBSV>(L, g, b);
+                out.y = obs_dword<OBSV>(L, g, b + 4);
+                *reinterpret_cast<uint2 *>(ob + b) = out;
+            }
+        }
+    }
+
+    // ---- rewards, done, scalars
+    if (KIND == K_STEP) {
+        if (lane < g.P)
+            a.rewards[(size_t)e * g.P + lane] = ((win >> lane) & 1u) ? 1 : (((lose >> lane) & 1u) ? -1 : 0);
+        if (lane == 0) a.dones[e] = done ? 1 : 0;
+    }
+    if (KIND != K_OBSERVE && lane == 0) {
+        EnvScalars *d = a.sc + e;
+        d->turn = s.turn;
+        d->episode = s.episode;
+        d->alive = s.alive;
+        d->finished = s.finished;
+        if (write_type) {
+#pragma unroll
+            for (int i = 0; i < kMaxP; ++i) d->gpos[i] = s.gpos[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- random legal actor (reading R15)
+__device__ __forceinline__ uint32_t legal_dirs(const Lds &L, const Geom &g, int c)
+{
+    const int r = div_w(c, g), col = c - r * g.W;
+    uint32_t m = 0;
+    if (r > 0 && L.type[c - g.W] != MOUNTAIN) m |= 1u;
+    if (r < g.H - 1 && L.type[c + g.W] != MOUNTAIN) m |= 2u;
+    if (col > 0 && L.type[c - 1] != MOUNTAIN) m |= 4u;
+    if (col < g.W - 1 && L.type[c + 1] != MOUNTAIN) m |= 8u;
+    return m;
+}
+
+__global__ __launch_bounds__(64) void k_sample(SampleArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = lane_id();
+    const int e = blockIdx.x;
+    const Geom g = a.g;
+    const Lds L = carve(smem, g);
+    const uint64_t env_id = a.env_base + (uint64_t)e;
+    const size_t cell0 = (size_t)e * g.S;
+    const uint32_t alive = a.sc[e].alive;
+
+    const int n16 = g.S >> 4;
+    for (int i = lane; i < n16; i += kWave) {
+        reinterpret_cast<uint4 *>(L.owner)[i] = reinterpret_cast<const uint4 *>(a.owner + cell0)[i];
+        reinterpret_cast<uint4 *>(L.type)[i] = reinterpret_cast<const uint4 *>(a.type + cell0)[i];
+    }
+    for (int i = lane; i < 4 * n16; i += kWave)
+        reinterpret_cast<uint4 *>(L.army)[i] = reinterpret_cast<const uint4 *>(a.army + cell0)[i];
+    wave_sync();
+
+    for (int p = 0; p < g.P; ++p) {
+        int32_t act = 0;
+        if ((alive >> p) & 1u) {
+            uint32_t mine = 0;
+            for (int c0 = 0; c0 < g.HW; c0 += kWave) {
+                const int c = c0 + lane;
+                if (c < g.HW && L.owner[c] == p && L.army[c] > 1) mine += 2u * (uint32_t)__popc(legal_dirs(L, g, c));
+            }
+            const uint32_t total = 1u + wave_sum_u32(mine);
+            const uint32_t idx = pick(draw32(a.actor_seed, DOM_ACTIONS, env_id, a.step_idx, (uint64_t)p, 0u), total);
+            if (idx > 0) {
+                const uint32_t t = idx - 1;
+                uint32_t run = 0;
+                for (int c0 = 0; c0 < g.HW; c0 += kWave) {
+                    const int c = c0 + lane;
+                    uint32_t dm = 0, n = 0;
+                    if (c < g.HW && L.owner[c] == p && L.army[c] > 1) {
+                        dm = legal_dirs(L, g, c);
+                        n = 2u * (uint32_t)__popc(dm);
+                    }
+                    const uint32_t incl = wave_incl_scan(n);
+                    const uint32_t chunk = (uint32_t)readlane((int)incl, kWave - 1);
+                    if (t < run + chunk) {
+                        const uint32_t lo = run + incl - n;
+                        const bool hit = n > 0 && lo <= t && t < run + incl;
+                        int code = 0;
+                        if (hit) {
+                            uint32_t jj = t - lo;
+                            const uint32_t nd = n >> 1;
+                            const int kbase = jj < nd ? 1 : 5;
+                            if (jj >= nd) jj -= nd;
+                            int dir = 0;
+                            for (int d = 0; d < 4; ++d) {
+                                if ((dm >> d) & 1u) {
+                                    if (jj == 0) { dir = d; break; }
+                                    --jj;
+                                }
+                            }
+                            code = c * 9 + kbase + dir;
+                        }
+                        const uint64_t hb = ballot(hit);
+                        act = readlane(code, (int)__ffsll((unsigned long long)hb) - 1);
+                        break;
+                    }
+                    run += chunk;
+                }
+            }
+        }
+        if (lane == 0) a.actions[(size_t)e * g.P + p] = act;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+uint32_t lds_bytes(const Geom &g) { return lds_bytes_for(g.S, g.P); }
+
+static int obs_variant(const Geom &g)
+{
+    if (g.HW % 16 == 0) return OBS_A16;
+    if (g.HW % 4 == 0) return OBS_A4;
+    return ((g.P * 8 * g.HW) % 16 == 0) ? OBS_A1C16 : OBS_A1C8;
+}
+
+template <int KIND, bool SB>
+static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
+{
+    const dim3 grid((unsigned)n_envs), block(kWave);
+    const uint32_t lds = lds_bytes(a.g);
+    switch (obs_variant(a.g)) {
+    case OBS_A16: hipLaunchKernelGGL((k_env<KIND, OBS_A16, SB>), grid, block, lds, stream, a); break;
+    case OBS_A4: hipLaunchKernelGGL((k_env<KIND, OBS_A4, SB>), grid, block, lds, stream, a); break;
+    case OBS_A1C16: hipLaunchKernelGGL((k_env<KIND, OBS_A1C16, SB>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_env<KIND, OBS_A1C8, SB>), grid, block, lds, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream)
+{
+    return (a.land != nullptr) ? launch_kind<K_STEP, true>(a, n_envs, stream)
+                               : launch_kind<K_STEP, false>(a, n_envs, stream);
+}
+
+hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream)
+{
+    return launch_kind<K_RESET, false>(a, n_envs, stream);
+}
+
+hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
+{
+    return launch_kind<K_OBSERVE, false>(a, n_envs, stream);
+}
+
+hipError_t launch_sample(const SampleArgs &a, int n_envs, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)n_envs), dim3(kWave), lds_bytes(a.g), stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace gen

@@ -1,0 +1,129 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+its host-side logic (layout, parameter checks, error reporting) behaves as
+documented.  No kernel is launched here, so these run without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+import paper_2606_23348_amd as gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "generals.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gen_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(gen.LIB_PATH):
+        pytest.fail("libgenerals.so is not built (run __graft_entry__.build())")
+    return gen.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("gen_reset", "gen_step", "gen_sample_actions", "gen_observe", "gen_get_state",
+              "gen_set_state", "gen_layout", "gen_state_bytes", "gen_last_error"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [f for f in declared_functions() if not hasattr(L, f)]
+    assert not missing, missing
+    # plain C names (no C++ mangling) in the dynamic symbol table
+    out = subprocess.run(["nm", "-D", "--defined-only", gen.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(gen_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_version(L):
+    assert gen.gen_version() == gen.GEN_LAYOUT_VERSION
+
+
+def test_default_params():
+    p = gen.gen_default_params(gen.GEN_1V1)
+    assert p.n_players == 2 and p.mountain_thresh == (2 ** 32) // 5
+    assert (p.cities_min, p.cities_max, p.city_army_min, p.city_army_max) == (9, 11, 40, 50)
+    assert gen.gen_default_params(gen.GEN_2V2).n_players == 4
+    assert gen.gen_default_params(gen.GEN_FFA, 8).n_players == 8
+    with pytest.raises(gen.GenError):
+        gen.gen_default_params(gen.GEN_FFA, 9)
+
+
+@pytest.mark.parametrize("E,H,W,mode,P", [(16, 10, 10, 0, 2), (65536, 24, 24, 0, 2), (16384, 25, 25, 2, 8),
+                                          (7, 3, 3, 1, 4), (3, 32, 32, 2, 5)])
+def test_layout(E, H, W, mode, P):
+    prm = gen.make_params(mode, P, cities_min=0, cities_max=min(11, H * W // 4))
+    st = gen.gen_layout(E, H, W, mode, prm, seed=9)
+    S = (H * W + 15) // 16 * 16
+    assert st.stride == S and st.n_players == P and st.version == 1
+    assert st.off_scalars == 0 and st.off_owner >= 32 * E
+    assert st.off_type - st.off_owner >= E * S and st.off_army - st.off_type >= E * S
+    assert st.bytes - st.off_army >= 4 * E * S
+    for off in (st.off_owner, st.off_type, st.off_army, st.bytes):
+        assert off % 256 == 0
+    assert gen.gen_state_bytes(E, H, W, mode, prm) == st.bytes
+
+
+@pytest.mark.parametrize("args", [(0, 10, 10, 0), (4, 2, 10, 0), (4, 10, 33, 0), (4, 10, 10, 7)])
+def test_layout_rejects_bad_shapes(args):
+    with pytest.raises(gen.GenError) as ei:
+        gen.gen_layout(*args)
+    assert ei.value.code == gen.GEN_EINVAL
+    assert gen.gen_last_error() != ""
+
+
+def test_layout_rejects_bad_params():
+    p = gen.make_params(gen.GEN_1V1, cities_min=5, cities_max=3)
+    with pytest.raises(gen.GenError):
+        gen.gen_layout(4, 10, 10, gen.GEN_1V1, p)
+    p = gen.make_params(gen.GEN_1V1)
+    p.reserved[2] = 1
+    with pytest.raises(gen.GenError):
+        gen.gen_layout(4, 10, 10, gen.GEN_1V1, p)
+    with pytest.raises(gen.GenError):            # FFA needs a player count
+        gen.gen_layout(4, 10, 10, gen.GEN_FFA, None)
+
+
+def test_calls_reject_missing_state_without_touching_the_device(L):
+    assert L.gen_step(None, None, None, None, None, None, None, None) == gen.GEN_EINVAL
+    assert "NULL" in gen.gen_last_error()
+    st = gen.gen_layout(4, 10, 10, gen.GEN_1V1)
+    assert L.gen_step(ctypes.byref(st), None, None, None, None, None, None, None) == gen.GEN_EINVAL
+    assert "device buffer" in gen.gen_last_error()
+    assert L.gen_reset(1, 0, 4, 10, 10, 0, None, None, 0, None, None, None) == gen.GEN_EINVAL
+
+
+def test_reset_rejects_small_buffer(L):
+    need = gen.gen_state_bytes(4, 10, 10, 0)
+    fake = ctypes.c_void_p(1 << 20)                # never dereferenced: the size check comes first
+    rc = L.gen_reset(1, 0, 4, 10, 10, 0, None, fake, need - 1, None, None, None)
+    assert rc == gen.GEN_ENOMEM
+
+
+def test_product_path_never_loads_the_oracle():
+    """Importing the binding must not import or load the CPU oracle."""
+    code = ("import sys, paper_2606_23348_amd as g; g.lib(); "
+            "assert 'oracle' not in sys.modules, 'oracle imported'; "
+            "maps = open('/proc/self/maps').read(); assert 'liboracle' not in maps; print('ok')")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert "ok" in out.stdout
+
+
+def test_one_hip_runtime_in_process():
+    """The library binds to the HIP runtime torch already loaded."""
+    code = ("import paper_2606_23348_amd as g; g.lib(); "
+            "import re; maps = open('/proc/self/maps').read(); "
+            "libs = set(re.findall(r'(\\S*libamdhip64[^\\s]*)', maps)); print(len(libs), sorted(libs))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[0] == "1", out.stdout

@@ -1,0 +1,298 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Both sides start from the same seeds and run independently: the oracle makes
+its own maps and its own random-actor draws; nothing the GPU produced is fed
+to the oracle.  Everything is integer, so every comparison is bit-exact.
+"""
+import hashlib
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import scenarios as scn
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("owner", "army", "type", "turn", "episode", "alive", "finished", "gpos")
+
+
+@pytest.fixture(scope="module")
+def gen():
+    import torch
+    import paper_2606_23348_amd as g
+    assert torch.cuda.is_available()
+    g.lib()
+    return g
+
+
+def ocfg(H, W, mode, P, seed, env_base=0, **prm):
+    return oracle.Config(H=H, W=W, mode=mode, P=P, seed=seed, env_base=env_base,
+                         **{k: v for k, v in prm.items() if k != "n_players"})
+
+
+def assert_state_equal(got, want, where=""):
+    for k in KEYS:
+        if not np.array_equal(got[k], want[k]):
+            bad = np.argwhere(got[k] != want[k])
+            raise AssertionError(f"{where}: field {k} differs at {bad[:5].tolist()} "
+                                 f"(gpu {got[k][tuple(bad[0])]}, oracle {want[k][tuple(bad[0])]})")
+
+
+def assert_obs_equal(got, want, where=""):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        raise AssertionError(f"{where}: obs differs at {len(bad)} places, first {bad[:5].tolist()}")
+
+
+def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=1, scoreboard=False):
+    """Step E envs on both sides for `steps` steps with the random actor;
+    compare actions, rewards, dones, observations and full state."""
+    import torch
+    params = gen.make_params(mode, P, **prm)
+    b = gen.Batch(E, H, W, mode, params, seed=seed, scoreboard=scoreboard)
+    cfg = ocfg(H, W, mode, P, seed, **prm)
+    ost, att = oracle.reset(cfg, E)
+    torch.cuda.synchronize()
+    assert_state_equal(b.get_state(), ost, "reset")
+    assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), "reset obs")
+    n_done = 0
+    for t in range(steps):
+        b.sample(actor_seed, t)
+        oact = oracle.sample(cfg, ost, actor_seed, t)
+        b.step()
+        orew, odone = oracle.step(cfg, ost, oact)
+        if t % check_every == 0 or t == steps - 1:
+            where = f"{H}x{W} mode {mode} P {P} step {t}"
+            assert np.array_equal(b.actions.cpu().numpy(), oact), where + " actions"
+            assert np.array_equal(b.rewards.cpu().numpy(), orew), where + " rewards"
+            assert np.array_equal(b.dones.cpu().numpy(), odone), where + " dones"
+            assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), where)
+            assert_state_equal(b.get_state(), ost, where)
+            if scoreboard:
+                land, army = oracle.scoreboard(cfg, ost)
+                assert np.array_equal(b.land.cpu().numpy(), land), where + " land"
+                assert np.array_equal(b.army.cpu().numpy(), army), where + " army"
+        n_done += int(odone.sum())
+    return n_done
+
+
+# ------------------------------------------------------------------ resets
+@pytest.mark.parametrize("H,W,mode,P,E", [
+    (10, 10, 0, 2, 16), (24, 24, 0, 2, 64), (25, 25, 2, 8, 32), (13, 11, 1, 4, 40), (3, 3, 0, 2, 20),
+    (32, 32, 2, 5, 9), (7, 19, 2, 3, 33), (16, 20, 1, 4, 50), (4, 9, 0, 2, 70)])
+def test_reset_matches_oracle(gen, H, W, mode, P, E):
+    import torch
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
+               cities_max=min(5, H * W // 4), min_general_dist=min(6, (H + W) // 3), auto_reset=1)
+    b = gen.Batch(E, H, W, mode, gen.make_params(mode, P, **prm), seed=H * 100 + W)
+    cfg = ocfg(H, W, mode, P, H * 100 + W, **prm)
+    ost, _ = oracle.reset(cfg, E)
+    torch.cuda.synchronize()
+    assert_state_equal(b.get_state(), ost, f"reset {H}x{W}")
+    assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), f"reset obs {H}x{W}")
+
+
+def test_reset_pregrow_and_env_base(gen):
+    import torch
+    wl = workloads.C3
+    prm = wl.params()
+    b = gen.Batch(24, 25, 25, 2, gen.make_params(2, 8, **prm), seed=3, env_base=1000)
+    cfg = ocfg(25, 25, 2, 8, 3, env_base=1000, **prm)
+    ost, _ = oracle.reset(cfg, 24)
+    torch.cuda.synchronize()
+    got = b.get_state()
+    assert_state_equal(got, ost, "pregrow")
+    g = got["army"][np.arange(24)[:, None], got["gpos"].astype(int)]
+    assert (g[::4] >= 100000).all() and (g[1::4] == 1).all()
+
+
+# ------------------------------------------------------------------ trajectories
+def test_c1_full_trajectory(gen):
+    """Workload plain-1v1-10x10-16env in full: 1,000 steps, every field every step."""
+    wl = workloads.C1
+    run_parity(gen, wl.H, wl.W, wl.mode, wl.P, wl.n_envs, wl.steps, wl.seed, wl.actor_seed, wl.params())
+
+
+@pytest.mark.parametrize("H,W,mode,P,E,steps", [
+    (24, 24, 0, 2, 48, 300),     # 16-byte aligned planes
+    (10, 10, 1, 4, 40, 300),     # 2v2, 4-byte aligned planes
+    (25, 25, 2, 8, 24, 200),     # FFA-8, unaligned planes, 16-byte chunks
+    (7, 9, 2, 3, 37, 300),       # FFA-3, unaligned planes, 8-byte chunks
+    (3, 3, 0, 2, 64, 200),       # tiny grid
+    (32, 32, 2, 4, 8, 150),      # largest grid
+    (11, 23, 1, 4, 30, 250),
+    (17, 6, 2, 6, 30, 250),
+])
+def test_trajectory_parity(gen, H, W, mode, P, E, steps):
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
+               cities_max=min(6, H * W // 4), min_general_dist=min(5, (H + W) // 3), auto_reset=1)
+    run_parity(gen, H, W, mode, P, E, steps, seed=H * 7 + W, actor_seed=99, prm=prm, check_every=1)
+
+
+def test_trajectory_scoreboard_and_no_autoreset(gen):
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
+               auto_reset=0)
+    n = run_parity(gen, 6, 6, 2, 4, 40, 400, seed=5, actor_seed=6, prm=prm, scoreboard=True)
+    assert n > 0          # some games ended and stayed frozen
+
+
+def test_many_episodes_autoreset(gen):
+    """Small FFA maps end quickly under random play: exercises capture,
+    elimination and in-kernel regeneration many times."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=0, cities_max=1, min_general_dist=2,
+               auto_reset=1)
+    n = run_parity(gen, 4, 4, 2, 3, 64, 500, seed=21, actor_seed=22, prm=prm)
+    assert n > 50
+
+
+# ------------------------------------------------------------------ scenarios through the ABI
+@pytest.mark.parametrize("sc", scn.load(), ids=lambda s: s["name"])
+def test_scenario_gpu(gen, sc):
+    import torch
+    H, W = len(sc["grid"]), len(sc["grid"][0].split())
+    P, mode = sc["P"], sc["mode"]
+    params = gen.make_params(mode, P, cities_min=0, cities_max=1, min_general_dist=1,
+                             auto_reset=sc.get("auto_reset", 0))
+    b = gen.Batch(1, H, W, mode, params, seed=7)
+    b.set_state(scn.initial_state(sc))
+    for k, stp in enumerate(sc["steps"]):
+        b.actions.copy_(torch.from_numpy(scn.encode_actions(stp, P)))
+        for _ in range(stp.get("repeat", 1)):
+            b.step()
+        got = b.get_state()
+        exp = stp["expect"]
+        assert scn.grid_of(got, H, W) == exp["grid"], f"step {k}"
+        assert int(got["turn"][0]) == exp["turn"]
+        assert b.rewards.cpu().numpy()[0].tolist() == exp["rewards"]
+        assert int(b.dones.cpu()[0]) == exp["done"]
+        assert int(got["alive"][0]) == exp["alive"]
+        cfg = ocfg(H, W, mode, P, 7, auto_reset=sc.get("auto_reset", 0))
+        assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, got), sc["name"])
+
+
+def test_autoreset_capture_returns_new_map(gen):
+    """R13: capture with auto-reset on: terminal rewards, done, next episode's map and obs."""
+    import torch
+    sc = next(s for s in scn.load() if s["name"] == "H6_general_capture_1v1")
+    prm = dict(cities_min=1, cities_max=2, min_general_dist=2, auto_reset=1)
+    b = gen.Batch(1, 3, 4, 0, gen.make_params(0, 2, **prm), seed=11, env_base=5)
+    cfg = ocfg(3, 4, 0, 2, 11, env_base=5, **prm)
+    ost = scn.initial_state(sc)
+    b.set_state(ost)
+    b.actions.copy_(torch.from_numpy(scn.encode_actions(sc["steps"][0], 2)))
+    b.step()
+    orew, odone = oracle.step(cfg, ost, scn.encode_actions(sc["steps"][0], 2))
+    assert b.rewards.cpu().numpy().tolist() == orew.tolist() == [[1, -1]]
+    assert int(b.dones.cpu()[0]) == 1
+    got = b.get_state()
+    assert got["episode"][0] == 1
+    assert_state_equal(got, ost, "auto-reset")
+    assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), "auto-reset obs")
+
+
+def test_saturation_growth_at_int32_max(gen):
+    import torch
+    b = gen.Batch(2, 5, 5, 0, gen.make_params(0, 2, cities_min=0, cities_max=1, min_general_dist=2), seed=1)
+    h = b.get_state()
+    h["army"][:, h["gpos"][0, 0]] = 2 ** 31 - 1
+    h["army"][1, :] = np.where(h["owner"][1] >= 0, 2 ** 31 - 3, h["army"][1])
+    b.set_state(h)
+    cfg = ocfg(5, 5, 0, 2, 1, cities_min=0, cities_max=1, min_general_dist=2)
+    for t in range(60):
+        b.actions.zero_()
+        b.step()
+        oracle.step(cfg, h, np.zeros((2, 2), np.int32))
+    assert_state_equal(b.get_state(), h, "saturation")
+    assert (b.get_state()["army"] <= 2 ** 31 - 1).all()
+
+
+def test_observe_entry_point(gen):
+    import torch
+    prm = dict(cities_min=2, cities_max=4, min_general_dist=4)
+    b = gen.Batch(32, 9, 14, 2, gen.make_params(2, 4, **prm), seed=4)
+    cfg = ocfg(9, 14, 2, 4, 4, **prm)
+    ost, _ = oracle.reset(cfg, 32)
+    for t in range(30):
+        b.sample(8, t)
+        b.step()
+        oracle.step(cfg, ost, oracle.sample(cfg, ost, 8, t))
+    obs2 = torch.empty_like(b.obs)
+    gen.gen_observe(b.st, obs2)
+    torch.cuda.synchronize()
+    assert_obs_equal(obs2.cpu().numpy(), oracle.observe(cfg, ost), "observe")
+    assert torch.equal(obs2, b.obs)
+
+
+def test_determinism(gen):
+    import torch
+
+    def digest():
+        b = gen.Batch(256, 16, 16, 1, gen.make_params(1, 4, cities_min=2, cities_max=4, min_general_dist=5), seed=3)
+        h = hashlib.sha256()
+        for t in range(50):
+            b.sample(4, t)
+            b.step()
+            h.update(b.obs.cpu().numpy().tobytes())
+        torch.cuda.synchronize()
+        return h.hexdigest()
+
+    assert digest() == digest()
+
+
+# ------------------------------------------------------------------ full-size workloads, sampled
+def _subset(E, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.arange(0, E, 1024), rng.choice(E, 32, replace=False)]))
+
+
+@pytest.mark.parametrize("name,steps_all,steps_sub", [("c2", 2, 120), ("c3", 2, 60)])
+def test_full_size_workload(gen, name, steps_all, steps_sub):
+    """The bench launch configuration at full size: every env for the first
+    steps, then a strided env subset every step; each env on the oracle side
+    is an independent run keyed by its global id."""
+    import torch
+    wl = workloads.PLAIN[name]
+    prm = wl.params()
+    E = wl.n_envs
+    b = gen.Batch(E, wl.H, wl.W, wl.mode, gen.make_params(wl.mode, wl.P, **prm), seed=wl.seed)
+    torch.cuda.synchronize()
+    cfg = ocfg(wl.H, wl.W, wl.mode, wl.P, wl.seed, **prm)
+    ost, _ = oracle.reset(cfg, E)
+    assert_state_equal(b.get_state(), ost, f"{name} reset")
+    for t in range(steps_all):
+        b.sample(wl.actor_seed, t)
+        b.step()
+        oact = oracle.sample(cfg, ost, wl.actor_seed, t)
+        orew, odone = oracle.step(cfg, ost, oact)
+        assert np.array_equal(b.actions.cpu().numpy(), oact)
+        assert np.array_equal(b.rewards.cpu().numpy(), orew)
+        assert np.array_equal(b.dones.cpu().numpy(), odone)
+        assert_state_equal(b.get_state(), ost, f"{name} step {t}")
+        for lo in range(0, E, 4096):                 # obs in chunks to bound host memory
+            sub = {k: v[lo:lo + 4096] for k, v in ost.items()}
+            c2 = ocfg(wl.H, wl.W, wl.mode, wl.P, wl.seed, env_base=lo, **prm)
+            assert_obs_equal(b.obs[lo:lo + 4096].cpu().numpy(), oracle.observe(c2, sub), f"{name} obs {t}")
+    # strided subset, independent oracle runs keyed by global env id
+    ids = _subset(E, 7)
+    subs = []
+    for e in ids:
+        c = ocfg(wl.H, wl.W, wl.mode, wl.P, wl.seed, env_base=int(e), **prm)
+        subs.append((c, {k: v[e:e + 1].copy() for k, v in ost.items()}))
+    for t in range(steps_all, steps_all + steps_sub):
+        b.sample(wl.actor_seed, t)
+        b.step()
+        gst = b.get_envs(ids)
+        gobs = b.obs[torch.from_numpy(ids).long().cuda()].cpu().numpy()
+        gact = b.actions.cpu().numpy()
+        grew, gdone = b.rewards.cpu().numpy(), b.dones.cpu().numpy()
+        for j, (c, s) in enumerate(subs):
+            e = ids[j]
+            a = oracle.sample(c, s, wl.actor_seed, t)
+            r, d = oracle.step(c, s, a)
+            where = f"{name} env {e} step {t}"
+            assert np.array_equal(gact[e], a[0]), where
+            assert np.array_equal(grew[e], r[0]) and gdone[e] == d[0], where
+            assert_state_equal({k: v[j:j + 1] for k, v in gst.items()}, s, where)
+            assert_obs_equal(gobs[j:j + 1], oracle.observe(c, s), where)
