@@ -245,8 +245,10 @@ __device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int 
 
 // All players' moves in rotating priority (reading R5), captures applied at
 // once by the whole wave (Section IV-E transfer, reading R9 halving).
-__device__ void resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_t my_action)
+// Returns true if a general was captured (the type row then changed).
+__device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_t my_action)
 {
+    bool captured = false;
     const int lane = lane_id();
     for (int j = 0; j < g.P; ++j) {
         const int i = (s.turn + j) % g.P;
@@ -263,9 +265,11 @@ __device__ void resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_
                 }
             }
             s.alive = (uint8_t)(s.alive & ~(1u << victim));
+            captured = true;
             wave_sync();
         }
     }
+    return captured;
 }
 
 // ---------------------------------------------------------------- fused env kernel
@@ -345,7 +349,7 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
         if (KIND == K_STEP) {
             if (!s.finished) {
                 const uint32_t alive0 = s.alive;
-                resolve_moves(L, g, s, act);
+                write_type = resolve_moves(L, g, s, act);
                 s.turn += 1;
                 grow2 = (s.turn & 1) == 0;
                 grow50 = (s.turn % 50) == 0;

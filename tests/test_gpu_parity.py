@@ -27,6 +27,10 @@ def gen():
     return g
 
 
+def gparams(gen, mode, P, prm):
+    return gen.make_params(mode, P, **{k: v for k, v in prm.items() if k != "n_players"})
+
+
 def ocfg(H, W, mode, P, seed, env_base=0, **prm):
     return oracle.Config(H=H, W=W, mode=mode, P=P, seed=seed, env_base=env_base,
                          **{k: v for k, v in prm.items() if k != "n_players"})
@@ -50,7 +54,7 @@ def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=
     """Step E envs on both sides for `steps` steps with the random actor;
     compare actions, rewards, dones, observations and full state."""
     import torch
-    params = gen.make_params(mode, P, **prm)
+    params = gparams(gen, mode, P, prm)
     b = gen.Batch(E, H, W, mode, params, seed=seed, scoreboard=scoreboard)
     cfg = ocfg(H, W, mode, P, seed, **prm)
     ost, att = oracle.reset(cfg, E)
@@ -86,7 +90,7 @@ def test_reset_matches_oracle(gen, H, W, mode, P, E):
     import torch
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
                cities_max=min(5, H * W // 4), min_general_dist=min(6, (H + W) // 3), auto_reset=1)
-    b = gen.Batch(E, H, W, mode, gen.make_params(mode, P, **prm), seed=H * 100 + W)
+    b = gen.Batch(E, H, W, mode, gparams(gen, mode, P, prm), seed=H * 100 + W)
     cfg = ocfg(H, W, mode, P, H * 100 + W, **prm)
     ost, _ = oracle.reset(cfg, E)
     torch.cuda.synchronize()
@@ -98,7 +102,7 @@ def test_reset_pregrow_and_env_base(gen):
     import torch
     wl = workloads.C3
     prm = wl.params()
-    b = gen.Batch(24, 25, 25, 2, gen.make_params(2, 8, **prm), seed=3, env_base=1000)
+    b = gen.Batch(24, 25, 25, 2, gparams(gen, 2, 8, prm), seed=3, env_base=1000)
     cfg = ocfg(25, 25, 2, 8, 3, env_base=1000, **prm)
     ost, _ = oracle.reset(cfg, 24)
     torch.cuda.synchronize()
@@ -177,7 +181,7 @@ def test_autoreset_capture_returns_new_map(gen):
     import torch
     sc = next(s for s in scn.load() if s["name"] == "H6_general_capture_1v1")
     prm = dict(cities_min=1, cities_max=2, min_general_dist=2, auto_reset=1)
-    b = gen.Batch(1, 3, 4, 0, gen.make_params(0, 2, **prm), seed=11, env_base=5)
+    b = gen.Batch(1, 3, 4, 0, gparams(gen, 0, 2, prm), seed=11, env_base=5)
     cfg = ocfg(3, 4, 0, 2, 11, env_base=5, **prm)
     ost = scn.initial_state(sc)
     b.set_state(ost)
@@ -211,7 +215,7 @@ def test_saturation_growth_at_int32_max(gen):
 def test_observe_entry_point(gen):
     import torch
     prm = dict(cities_min=2, cities_max=4, min_general_dist=4)
-    b = gen.Batch(32, 9, 14, 2, gen.make_params(2, 4, **prm), seed=4)
+    b = gen.Batch(32, 9, 14, 2, gparams(gen, 2, 4, prm), seed=4)
     cfg = ocfg(9, 14, 2, 4, 4, **prm)
     ost, _ = oracle.reset(cfg, 32)
     for t in range(30):

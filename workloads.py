@@ -61,7 +61,7 @@ class Workload:
 
     def params(self) -> dict:
         """Generator parameters as keyword arguments (same names on both sides)."""
-        return dict(n_players=self.P, mountain_thresh=self.thresh, cities_min=self.cities_min,
+        return dict(mountain_thresh=self.thresh, cities_min=self.cities_min,
                     cities_max=self.cities_max, city_army_min=self.city_army_min,
                     city_army_max=self.city_army_max, min_general_dist=self.min_general_dist,
                     auto_reset=self.auto_reset, pregrow=self.pregrow)
