@@ -3,9 +3,10 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
 
 One timed step is one pass of the whole hot path over every env of the
-workload: the random legal actor (gen_sample_actions) followed by the
-environment step (gen_step: moves, combat, captures, growth, terminal,
-auto-reset, fog, observation, state store), with all inputs resident in HBM.
+workload, one launch of gen_step_sample: the environment step (moves,
+combat, captures, growth, terminal, auto-reset, fog, observation, state
+store) followed by the random legal actor drawing the next step's actions,
+with all inputs resident in HBM.
 `value` is frames per second (1 frame = 1 env advanced 1 step).
 
 The JSON line also carries
@@ -49,16 +50,16 @@ def kernel_hash() -> str:
 def step_bytes(wl) -> dict:
     """Algorithmic HBM bytes per frame of the step kernel and of the actor.
 
-    step reads the env's state (owner int8, type uint8, army int32 per cell,
-    the 32-byte scalar record) and its P actions; it writes owner and army,
-    the uint8 [P][8][H][W] observation, P rewards, the done byte and the
-    10 live bytes of the scalar record (type is written only on a reset).
+    The fused step reads the env's state (owner int8, type uint8, army int32
+    per cell, the 32-byte scalar record) and its P actions; it writes owner
+    and army, the uint8 [P][8][H][W] observation, P rewards, the done byte,
+    the 10 live bytes of the scalar record and the P actions of the next step
+    (type is written only after a capture or a reset).
     """
     HW, P = wl.H * wl.W, wl.P
     read = HW * (1 + 1 + 4) + 32 + 4 * P
-    write = HW * (1 + 4) + P * 8 * HW + 4 * P + 1 + 10
-    actor = HW * (1 + 1 + 4) + 32 + 4 * P
-    return {"step_read": read, "step_write": write, "step": read + write, "actor": actor}
+    write = HW * (1 + 4) + P * 8 * HW + 4 * P + 1 + 10 + 4 * P      # + the next step's actions
+    return {"step_read": read, "step_write": write, "step": read + write}
 
 
 def traffic_for(wl_name: str, n_launch_frames: int):
@@ -73,6 +74,25 @@ def traffic_for(wl_name: str, n_launch_frames: int):
     if not rec or rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def copy_ceiling_gbs(torch, n_bytes: int = 1 << 30, reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy (read + write bytes / time):
+    the practical streaming ceiling next to the 8 TB/s peak."""
+    src = torch.empty(n_bytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n_bytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def cpu_baseline(wl, n_envs: int, n_steps: int) -> dict:
@@ -127,9 +147,10 @@ def main() -> int:
     b = gen.Batch(E, wl.H, wl.W, wl.mode, params, seed=wl.seed)
     stream = torch.cuda.current_stream()
 
+    # actions of step 0; afterwards every launch steps all envs and samples the next actions
+    b.sample(wl.actor_seed, 0)
     for t in range(W):
-        b.sample(wl.actor_seed, t)
-        b.step()
+        b.step_sample(wl.actor_seed, t + 1)
     torch.cuda.synchronize()
 
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
@@ -137,9 +158,8 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(K):
-        b.sample(wl.actor_seed, W + t)
         ev0[t].record(stream)
-        b.step()
+        b.step_sample(wl.actor_seed, W + t + 1)
         ev1[t].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -172,8 +192,9 @@ def main() -> int:
                            "p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_env<STEP> (gen_step)", "algorithmic_bytes_per_frame": by["step"],
-                     "frames_per_launch": E},
+                     "kernel": "k_env<STEP, actor fused> (gen_step_sample)",
+                     "algorithmic_bytes_per_frame": by["step"],
+                     "frames_per_launch": E, "copy_ceiling_gbs": copy_ceiling_gbs(torch)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_envs, args.cpu_steps)

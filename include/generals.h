@@ -173,6 +173,16 @@ int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int3
 int gen_sample_actions(const gen_state *st, uint64_t actor_seed, uint64_t step_idx, int32_t *d_actions,
                        void *stream);
 
+/* gen_step followed by gen_sample_actions in one launch: the step consumes
+ * d_actions, then the random legal actor samples the next step's actions
+ * (Philox counter step index `next_step_idx`) from the post-step state --
+ * after growth and any auto-reset -- and writes them back into d_actions.
+ * Results are identical to the two separate calls; the state is read from
+ * HBM once instead of twice. */
+int gen_step_sample(const gen_state *st, int32_t *d_actions, uint64_t actor_seed, uint64_t next_step_idx,
+                    uint8_t *d_obs, int32_t *d_rewards, uint8_t *d_dones, int32_t *d_land, int64_t *d_army,
+                    void *stream);
+
 /* Observation of the current state (no state change). */
 int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
 

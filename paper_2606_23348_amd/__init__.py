@@ -74,11 +74,12 @@ def lib() -> ctypes.CDLL:
     L.gen_reset.argtypes = [u64, u64, i32, i32, i32, i32, P(gen_params), vp, u64, vp, vp, P(gen_state)]
     L.gen_step.argtypes = [P(gen_state), vp, vp, vp, vp, vp, vp, vp]
     L.gen_sample_actions.argtypes = [P(gen_state), u64, u64, vp, vp]
+    L.gen_step_sample.argtypes = [P(gen_state), vp, u64, u64, vp, vp, vp, vp, vp, vp]
     L.gen_observe.argtypes = [P(gen_state), vp, vp]
     L.gen_get_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_set_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_get_envs.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
-    for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_sample_actions",
+    for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
               "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -154,6 +155,13 @@ def gen_reset(seed: int, env_base: int, n_envs: int, H: int, W: int, mode: int, 
 def gen_step(st: gen_state, actions, obs, rewards, dones, land=None, army=None, stream=None):
     _check(lib().gen_step(ctypes.byref(st), _ptr(actions), _ptr(obs), _ptr(rewards), _ptr(dones),
                           _ptr(land), _ptr(army), _stream(stream)))
+
+
+def gen_step_sample(st: gen_state, actions, actor_seed: int, next_step_idx: int, obs, rewards, dones,
+                    land=None, army=None, stream=None):
+    """gen_step, then the random actor for step `next_step_idx` into `actions` (one launch)."""
+    _check(lib().gen_step_sample(ctypes.byref(st), _ptr(actions), actor_seed, next_step_idx, _ptr(obs),
+                                 _ptr(rewards), _ptr(dones), _ptr(land), _ptr(army), _stream(stream)))
 
 
 def gen_sample_actions(st: gen_state, actor_seed: int, step_idx: int, actions, stream=None):
@@ -232,6 +240,10 @@ class Batch:
 
     def step(self, stream=None):
         gen_step(self.st, self.actions, self.obs, self.rewards, self.dones, self.land, self.army, stream)
+
+    def step_sample(self, actor_seed: int, next_step_idx: int, stream=None):
+        gen_step_sample(self.st, self.actions, actor_seed, next_step_idx, self.obs, self.rewards, self.dones,
+                        self.land, self.army, stream)
 
     def observe(self, stream=None):
         gen_observe(self.st, self.obs, stream)

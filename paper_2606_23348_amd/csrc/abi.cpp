@@ -249,6 +249,33 @@ int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int3
     return ok();
 }
 
+int gen_step_sample(const gen_state *st, int32_t *d_actions, uint64_t actor_seed, uint64_t next_step_idx,
+                    uint8_t *d_obs, int32_t *d_rewards, uint8_t *d_dones, int32_t *d_land, int64_t *d_army,
+                    void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (d_actions == nullptr || d_rewards == nullptr || d_dones == nullptr)
+        return fail(GEN_EINVAL, "d_actions, d_rewards and d_dones are required");
+    if ((d_land == nullptr) != (d_army == nullptr)) return fail(GEN_EINVAL, "d_land and d_army go together");
+    if (check_obs_ptr(*st, d_obs) != GEN_OK) return GEN_EINVAL;
+    if (!aligned(d_actions, 4) || !aligned(d_rewards, 4) || (d_army && !aligned(d_army, 8)) ||
+        (d_land && !aligned(d_land, 4)))
+        return fail(GEN_EINVAL, "misaligned action, reward or scoreboard pointer");
+    gen::EnvArgs a = env_args(*st);
+    a.actions = d_actions;
+    a.next_actions = d_actions;
+    a.actor_seed = actor_seed;
+    a.step_idx = next_step_idx;
+    a.obs = d_obs;
+    a.rewards = d_rewards;
+    a.dones = d_dones;
+    a.land = d_land;
+    a.army_tot = d_army;
+    hipError_t e = gen::launch_step(a, st->n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return ok();
+}
+
 int gen_sample_actions(const gen_state *st, uint64_t actor_seed, uint64_t step_idx, int32_t *d_actions, void *stream)
 {
     if (check_state(st) != GEN_OK) return GEN_EINVAL;

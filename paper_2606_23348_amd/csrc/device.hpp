@@ -53,7 +53,9 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Value of `v` held by lane `src` (any lane index; taken mod 64).
+// Value of `v` held by lane `src` (any lane index; taken mod 64).  Call it
+// with every lane of the wave active: ds_bpermute returns 0 for a source
+// lane that is masked off, so a shuffle inside a divergent branch loses data.
 __device__ __forceinline__ uint32_t shfl32(uint32_t v, int src)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)v);

@@ -22,6 +22,8 @@ struct EnvArgs {
     uint8_t *dones;
     int32_t *land;
     int64_t *army_tot;
+    int32_t *next_actions;        // fused actor output (nullptr: no actor)
+    uint64_t actor_seed, step_idx;
 };
 
 struct SampleArgs {

@@ -12,7 +12,7 @@ namespace gen {
 // Per env, S = padded cells per row (multiple of 16):
 //   army  int32 [S] | owner int8 [S] | type uint8 [S] | armyc uint8 [S] + 16
 //   code  uint8 [P*S] + 16            (per player, bits = obs channels 0..6)
-//   tbm   u64 [P][16]                 (team-owned cell bitmaps)
+//   obm   u64 [P][16]                 (cells owned by each player)
 //   vis   u64 [P][16]                 (visible cell bitmaps)
 //   gbm   u64 [3][16] + int32 [8]      (map generator scratch bitmaps, general cells)
 struct Lds {
@@ -21,7 +21,7 @@ struct Lds {
     uint8_t *type;
     uint8_t *armyc;
     uint8_t *code;
-    uint64_t *tbm, *vis, *gbm;
+    uint64_t *obm, *vis, *gbm;
 };
 
 __host__ __device__ inline uint32_t lds_bytes_for(int S, int P)
@@ -38,7 +38,7 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
     L.type = smem + o; o += g.S;
     L.armyc = smem + o; o += g.S + 16;
     L.code = smem + o; o += g.P * g.S + 16;
-    L.tbm = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
+    L.obm = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.vis = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.gbm = reinterpret_cast<uint64_t *>(smem + o);
     return L;
@@ -272,6 +272,76 @@ __device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_
     return captured;
 }
 
+// ---------------------------------------------------------------- random legal actor (reading R15)
+// Lane (p, w) holds word w of player p's bitmaps.  The legal moves of one
+// direction are the player's cells with more than one unit whose neighbour
+// in that direction is on the grid and not a mountain: one AND with the
+// shifted passable bitmap.  A cell with d legal directions contributes 2d
+// entries (all-but-one, then half) to the list [pass, (cell, k)...]; the
+// uniform pick is located by a prefix over words and a binary search over
+// the bits of one word.  own: [P][16] words, pass/big: [16] words in LDS.
+__device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *pass, const uint64_t *big,
+                           uint32_t alive, uint64_t actor_seed, uint64_t step_idx, uint64_t env_id, int32_t *act_out)
+{
+    const int lane = lane_id();
+    const int NW = g.NW, W = g.W;
+    const int ppr = kWave / NW;
+    const int lp = lane / NW, w = lane - lp * NW;
+    const ColMasks cm = col_masks(w, g);
+    const uint64_t pw = pass[w];
+    const uint64_t pprev = w > 0 ? pass[w - 1] : 0ull, pnext = w < NW - 1 ? pass[w + 1] : 0ull;
+    const uint64_t up_ok = (pw << W) | (pprev >> (64 - W));          // cell c with c - W passable
+    const uint64_t dn_ok = (pw >> W) | (pnext << (64 - W));          // c + W passable
+    const uint64_t lf_ok = ((pw << 1) | (pprev >> 63)) & ~cm.col0;   // c - 1 passable, same row
+    const uint64_t rt_ok = ((pw >> 1) | (pnext << 63)) & ~cm.colL;   // c + 1 passable, same row
+    const uint64_t bw = big[w];
+    for (int p0 = 0; p0 < g.P; p0 += ppr) {
+        const int p = p0 + lp;
+        const bool valid = lp < ppr && p < g.P;
+        const uint64_t src = (valid && ((alive >> p) & 1u)) ? (own[p * 16 + w] & bw) : 0ull;
+        const uint64_t lu = src & up_ok, ld = src & dn_ok, ll = src & lf_ok, lr = src & rt_ok;
+        const uint32_t cnt = 2u * (uint32_t)(__popcll(lu) + __popcll(ld) + __popcll(ll) + __popcll(lr));
+        const uint32_t incl = wave_incl_scan(cnt);
+        const int first = lp * NW;
+        // every lane takes part in both shuffles (an inactive source lane would read as 0)
+        const uint32_t below = shfl32(incl, first - 1);
+        const uint32_t upto = shfl32(incl, first + NW - 1);
+        const uint32_t before = first > 0 ? below : 0u;
+        const uint32_t total = upto - before;
+        const uint32_t excl = incl - cnt - before;
+        const uint32_t r = draw32(actor_seed, DOM_ACTIONS, env_id, step_idx, (uint64_t)p, 0u);
+        const uint32_t idx = pick(r, 1u + total);
+        const bool mine = valid && idx > 0 && excl <= idx - 1 && idx - 1 < excl + cnt;
+        if (mine) {
+            const uint32_t t = idx - 1 - excl;
+            int b = 0;
+            for (int st = 32; st >= 1; st >>= 1) {
+                const uint64_t m = (1ull << (b + st)) - 1ull;
+                const uint32_t pre = 2u * (uint32_t)(__popcll(lu & m) + __popcll(ld & m) + __popcll(ll & m) +
+                                                     __popcll(lr & m));
+                if (pre <= t) b += st;
+            }
+            const uint64_t m = (1ull << b) - 1ull;
+            uint32_t j = t - 2u * (uint32_t)(__popcll(lu & m) + __popcll(ld & m) + __popcll(ll & m) + __popcll(lr & m));
+            const uint32_t dirs = (uint32_t)((lu >> b) & 1ull) | ((uint32_t)((ld >> b) & 1ull) << 1) |
+                                  ((uint32_t)((ll >> b) & 1ull) << 2) | ((uint32_t)((lr >> b) & 1ull) << 3);
+            const uint32_t nd = (uint32_t)__popc(dirs);
+            int kbase = 1;
+            if (j >= nd) { j -= nd; kbase = 5; }
+            int dir = 0;
+            for (int d = 0, seen = 0; d < 4; ++d) {
+                if ((dirs >> d) & 1u) {
+                    if ((uint32_t)seen == j) { dir = d; break; }
+                    ++seen;
+                }
+            }
+            act_out[p] = (w * 64 + b) * 9 + kbase + dir;
+        } else if (valid && w == 0 && idx == 0) {
+            act_out[p] = 0;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- fused env kernel
 enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
 enum { OBS_A16 = 0, OBS_A4 = 1, OBS_A1C16 = 2, OBS_A1C8 = 3 };
@@ -313,7 +383,7 @@ __device__ __forceinline__ uint32_t obs_dword(const Lds &L, const Geom &g, uint3
     }
 }
 
-template <int KIND, int OBSV, bool SB>
+template <int KIND, int OBSV, bool SB, bool ACT>
 __global__ __launch_bounds__(64) void k_env(EnvArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -439,14 +509,20 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
         }
     }
 
-    // ---- per-player team bitmaps (ballot per 64 cells)
+    // ---- per-player owned-cell bitmaps (one ballot per player per 64 cells);
+    // with the fused actor also the passable and army > 1 bitmaps
     for (int w = 0; w < g.NW; ++w) {
         const int c = w * 64 + lane;
-        const int o = c < g.HW ? (int)L.owner[c] : -1;
+        const bool real = c < g.HW;
+        const int o = real ? (int)L.owner[c] : -1;
         for (int p = 0; p < g.P; ++p) {
-            const bool in = (o == p) || (g.mode == MODE_2V2 && o == (p ^ 2));
-            const uint64_t m = ballot(in);
-            if (lane == 0) L.tbm[p * 16 + w] = m;
+            const uint64_t m = ballot(o == p);
+            if (lane == 0) L.obm[p * 16 + w] = m;
+        }
+        if (ACT) {
+            const uint64_t pm = ballot(real && L.type[c] != MOUNTAIN);
+            const uint64_t bm = ballot(real && L.armyc[c] > 1);
+            if (lane == 0) { L.gbm[w] = pm; L.gbm[16 + w] = bm; }
         }
     }
     wave_sync();
@@ -459,7 +535,8 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
         for (int p0 = 0; p0 < g.P; p0 += ppr) {
             const int p = p0 + lp;
             const bool valid = lp < ppr && p < g.P;
-            const uint64_t m = valid ? L.tbm[p * 16 + w] : 0ull;
+            uint64_t m = valid ? L.obm[p * 16 + w] : 0ull;
+            if (valid && g.mode == MODE_2V2) m |= L.obm[(p ^ 2) * 16 + w];   // team vision (R10)
             uint64_t mp = shfl64(m, lane - 1), mn = shfl64(m, lane + 1);
             if (w == 0) mp = 0ull;
             if (w == g.NW - 1) mn = 0ull;
@@ -542,6 +619,10 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
         }
     }
 
+    // ---- fused random actor for the next step, on the final state
+    if (ACT) actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, a.actor_seed, a.step_idx, env_id,
+                        a.next_actions + (size_t)e * g.P);
+
     // ---- rewards, done, scalars
     if (KIND == K_STEP) {
         if (lane < g.P)
@@ -561,18 +642,7 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
     }
 }
 
-// ---------------------------------------------------------------- random legal actor (reading R15)
-__device__ __forceinline__ uint32_t legal_dirs(const Lds &L, const Geom &g, int c)
-{
-    const int r = div_w(c, g), col = c - r * g.W;
-    uint32_t m = 0;
-    if (r > 0 && L.type[c - g.W] != MOUNTAIN) m |= 1u;
-    if (r < g.H - 1 && L.type[c + g.W] != MOUNTAIN) m |= 2u;
-    if (col > 0 && L.type[c - 1] != MOUNTAIN) m |= 4u;
-    if (col < g.W - 1 && L.type[c + 1] != MOUNTAIN) m |= 8u;
-    return m;
-}
-
+// ---------------------------------------------------------------- standalone actor
 __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -583,66 +653,28 @@ __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
     const uint64_t env_id = a.env_base + (uint64_t)e;
     const size_t cell0 = (size_t)e * g.S;
     const uint32_t alive = a.sc[e].alive;
-
+    // owner and type rows into LDS; army only as the "more than one unit" bit
     const int n16 = g.S >> 4;
     for (int i = lane; i < n16; i += kWave) {
         reinterpret_cast<uint4 *>(L.owner)[i] = reinterpret_cast<const uint4 *>(a.owner + cell0)[i];
         reinterpret_cast<uint4 *>(L.type)[i] = reinterpret_cast<const uint4 *>(a.type + cell0)[i];
     }
-    for (int i = lane; i < 4 * n16; i += kWave)
-        reinterpret_cast<uint4 *>(L.army)[i] = reinterpret_cast<const uint4 *>(a.army + cell0)[i];
     wave_sync();
-
-    for (int p = 0; p < g.P; ++p) {
-        int32_t act = 0;
-        if ((alive >> p) & 1u) {
-            uint32_t mine = 0;
-            for (int c0 = 0; c0 < g.HW; c0 += kWave) {
-                const int c = c0 + lane;
-                if (c < g.HW && L.owner[c] == p && L.army[c] > 1) mine += 2u * (uint32_t)__popc(legal_dirs(L, g, c));
-            }
-            const uint32_t total = 1u + wave_sum_u32(mine);
-            const uint32_t idx = pick(draw32(a.actor_seed, DOM_ACTIONS, env_id, a.step_idx, (uint64_t)p, 0u), total);
-            if (idx > 0) {
-                const uint32_t t = idx - 1;
-                uint32_t run = 0;
-                for (int c0 = 0; c0 < g.HW; c0 += kWave) {
-                    const int c = c0 + lane;
-                    uint32_t dm = 0, n = 0;
-                    if (c < g.HW && L.owner[c] == p && L.army[c] > 1) {
-                        dm = legal_dirs(L, g, c);
-                        n = 2u * (uint32_t)__popc(dm);
-                    }
-                    const uint32_t incl = wave_incl_scan(n);
-                    const uint32_t chunk = (uint32_t)readlane((int)incl, kWave - 1);
-                    if (t < run + chunk) {
-                        const uint32_t lo = run + incl - n;
-                        const bool hit = n > 0 && lo <= t && t < run + incl;
-                        int code = 0;
-                        if (hit) {
-                            uint32_t jj = t - lo;
-                            const uint32_t nd = n >> 1;
-                            const int kbase = jj < nd ? 1 : 5;
-                            if (jj >= nd) jj -= nd;
-                            int dir = 0;
-                            for (int d = 0; d < 4; ++d) {
-                                if ((dm >> d) & 1u) {
-                                    if (jj == 0) { dir = d; break; }
-                                    --jj;
-                                }
-                            }
-                            code = c * 9 + kbase + dir;
-                        }
-                        const uint64_t hb = ballot(hit);
-                        act = readlane(code, (int)__ffsll((unsigned long long)hb) - 1);
-                        break;
-                    }
-                    run += chunk;
-                }
-            }
+    for (int w = 0; w < g.NW; ++w) {
+        const int c = w * 64 + lane;
+        const bool real = c < g.HW;
+        const int o = real ? (int)L.owner[c] : -1;
+        const bool many = real && a.army[cell0 + c] > 1;
+        for (int p = 0; p < g.P; ++p) {
+            const uint64_t m = ballot(o == p);
+            if (lane == 0) L.obm[p * 16 + w] = m;
         }
-        if (lane == 0) a.actions[(size_t)e * g.P + p] = act;
+        const uint64_t pm = ballot(real && L.type[c] != MOUNTAIN);
+        const uint64_t bm = ballot(many);
+        if (lane == 0) { L.gbm[w] = pm; L.gbm[16 + w] = bm; }
     }
+    wave_sync();
+    actor_wave(g, L.obm, L.gbm, L.gbm + 16, alive, a.actor_seed, a.step_idx, env_id, a.actions + (size_t)e * g.P);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -655,34 +687,37 @@ static int obs_variant(const Geom &g)
     return ((g.P * 8 * g.HW) % 16 == 0) ? OBS_A1C16 : OBS_A1C8;
 }
 
-template <int KIND, bool SB>
+template <int KIND, bool SB, bool ACT>
 static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
     const dim3 grid((unsigned)n_envs), block(kWave);
     const uint32_t lds = lds_bytes(a.g);
     switch (obs_variant(a.g)) {
-    case OBS_A16: hipLaunchKernelGGL((k_env<KIND, OBS_A16, SB>), grid, block, lds, stream, a); break;
-    case OBS_A4: hipLaunchKernelGGL((k_env<KIND, OBS_A4, SB>), grid, block, lds, stream, a); break;
-    case OBS_A1C16: hipLaunchKernelGGL((k_env<KIND, OBS_A1C16, SB>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_env<KIND, OBS_A1C8, SB>), grid, block, lds, stream, a); break;
+    case OBS_A16: hipLaunchKernelGGL((k_env<KIND, OBS_A16, SB, ACT>), grid, block, lds, stream, a); break;
+    case OBS_A4: hipLaunchKernelGGL((k_env<KIND, OBS_A4, SB, ACT>), grid, block, lds, stream, a); break;
+    case OBS_A1C16: hipLaunchKernelGGL((k_env<KIND, OBS_A1C16, SB, ACT>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_env<KIND, OBS_A1C8, SB, ACT>), grid, block, lds, stream, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
-    return (a.land != nullptr) ? launch_kind<K_STEP, true>(a, n_envs, stream)
-                               : launch_kind<K_STEP, false>(a, n_envs, stream);
+    if (a.next_actions != nullptr)
+        return (a.land != nullptr) ? launch_kind<K_STEP, true, true>(a, n_envs, stream)
+                                   : launch_kind<K_STEP, false, true>(a, n_envs, stream);
+    return (a.land != nullptr) ? launch_kind<K_STEP, true, false>(a, n_envs, stream)
+                               : launch_kind<K_STEP, false, false>(a, n_envs, stream);
 }
 
 hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
-    return launch_kind<K_RESET, false>(a, n_envs, stream);
+    return launch_kind<K_RESET, false, false>(a, n_envs, stream);
 }
 
 hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
-    return launch_kind<K_OBSERVE, false>(a, n_envs, stream);
+    return launch_kind<K_OBSERVE, false, false>(a, n_envs, stream);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int n_envs, hipStream_t stream)

@@ -50,9 +50,12 @@ def assert_obs_equal(got, want, where=""):
         raise AssertionError(f"{where}: obs differs at {len(bad)} places, first {bad[:5].tolist()}")
 
 
-def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=1, scoreboard=False):
+def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=1, scoreboard=False,
+               fused=False):
     """Step E envs on both sides for `steps` steps with the random actor;
-    compare actions, rewards, dones, observations and full state."""
+    compare actions, rewards, dones, observations and full state.  With
+    fused=True the GPU runs gen_step_sample (step + next actions in one
+    launch) and its actions are compared with the oracle's next draw."""
     import torch
     params = gparams(gen, mode, P, prm)
     b = gen.Batch(E, H, W, mode, params, seed=seed, scoreboard=scoreboard)
@@ -62,14 +65,23 @@ def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=
     assert_state_equal(b.get_state(), ost, "reset")
     assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), "reset obs")
     n_done = 0
+    if fused:
+        b.sample(actor_seed, 0)
     for t in range(steps):
-        b.sample(actor_seed, t)
         oact = oracle.sample(cfg, ost, actor_seed, t)
-        b.step()
+        if fused:
+            b.step_sample(actor_seed, t + 1)
+        else:
+            b.sample(actor_seed, t)
+            if t % check_every == 0 or t == steps - 1:
+                assert np.array_equal(b.actions.cpu().numpy(), oact), f"step {t} actions"
+            b.step()
         orew, odone = oracle.step(cfg, ost, oact)
         if t % check_every == 0 or t == steps - 1:
             where = f"{H}x{W} mode {mode} P {P} step {t}"
-            assert np.array_equal(b.actions.cpu().numpy(), oact), where + " actions"
+            if fused:
+                assert np.array_equal(b.actions.cpu().numpy(), oracle.sample(cfg, ost, actor_seed, t + 1)), \
+                    where + " next actions"
             assert np.array_equal(b.rewards.cpu().numpy(), orew), where + " rewards"
             assert np.array_equal(b.dones.cpu().numpy(), odone), where + " dones"
             assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), where)
@@ -129,10 +141,11 @@ def test_c1_full_trajectory(gen):
     (11, 23, 1, 4, 30, 250),
     (17, 6, 2, 6, 30, 250),
 ])
-def test_trajectory_parity(gen, H, W, mode, P, E, steps):
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
                cities_max=min(6, H * W // 4), min_general_dist=min(5, (H + W) // 3), auto_reset=1)
-    run_parity(gen, H, W, mode, P, E, steps, seed=H * 7 + W, actor_seed=99, prm=prm, check_every=1)
+    run_parity(gen, H, W, mode, P, E, steps, seed=H * 7 + W, actor_seed=99, prm=prm, check_every=1, fused=fused)
 
 
 def test_trajectory_scoreboard_and_no_autoreset(gen):
@@ -142,13 +155,25 @@ def test_trajectory_scoreboard_and_no_autoreset(gen):
     assert n > 0          # some games ended and stayed frozen
 
 
-def test_many_episodes_autoreset(gen):
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_many_episodes_autoreset(gen, fused):
     """Small FFA maps end quickly under random play: exercises capture,
     elimination and in-kernel regeneration many times."""
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=0, cities_max=1, min_general_dist=2,
                auto_reset=1)
-    n = run_parity(gen, 4, 4, 2, 3, 64, 500, seed=21, actor_seed=22, prm=prm)
+    n = run_parity(gen, 4, 4, 2, 3, 64, 500, seed=21, actor_seed=22, prm=prm, fused=fused)
     assert n > 50
+
+
+def test_c1_full_trajectory_fused(gen):
+    wl = workloads.C1
+    run_parity(gen, wl.H, wl.W, wl.mode, wl.P, wl.n_envs, wl.steps, wl.seed, wl.actor_seed, wl.params(), fused=True)
+
+
+def test_fused_scoreboard_2v2(gen):
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
+               auto_reset=0)
+    run_parity(gen, 8, 6, 1, 4, 40, 300, seed=15, actor_seed=16, prm=prm, scoreboard=True, fused=True)
 
 
 # ------------------------------------------------------------------ scenarios through the ABI
@@ -265,12 +290,13 @@ def test_full_size_workload(gen, name, steps_all, steps_sub):
     cfg = ocfg(wl.H, wl.W, wl.mode, wl.P, wl.seed, **prm)
     ost, _ = oracle.reset(cfg, E)
     assert_state_equal(b.get_state(), ost, f"{name} reset")
+    b.sample(wl.actor_seed, 0)
+    assert np.array_equal(b.actions.cpu().numpy(), oracle.sample(cfg, ost, wl.actor_seed, 0))
     for t in range(steps_all):
-        b.sample(wl.actor_seed, t)
-        b.step()
+        b.step_sample(wl.actor_seed, t + 1)               # the launch bench.py times
         oact = oracle.sample(cfg, ost, wl.actor_seed, t)
         orew, odone = oracle.step(cfg, ost, oact)
-        assert np.array_equal(b.actions.cpu().numpy(), oact)
+        assert np.array_equal(b.actions.cpu().numpy(), oracle.sample(cfg, ost, wl.actor_seed, t + 1))
         assert np.array_equal(b.rewards.cpu().numpy(), orew)
         assert np.array_equal(b.dones.cpu().numpy(), odone)
         assert_state_equal(b.get_state(), ost, f"{name} step {t}")
@@ -285,8 +311,7 @@ def test_full_size_workload(gen, name, steps_all, steps_sub):
         c = ocfg(wl.H, wl.W, wl.mode, wl.P, wl.seed, env_base=int(e), **prm)
         subs.append((c, {k: v[e:e + 1].copy() for k, v in ost.items()}))
     for t in range(steps_all, steps_all + steps_sub):
-        b.sample(wl.actor_seed, t)
-        b.step()
+        b.step_sample(wl.actor_seed, t + 1)
         gst = b.get_envs(ids)
         gobs = b.obs[torch.from_numpy(ids).long().cuda()].cpu().numpy()
         gact = b.actions.cpu().numpy()
@@ -296,7 +321,7 @@ def test_full_size_workload(gen, name, steps_all, steps_sub):
             a = oracle.sample(c, s, wl.actor_seed, t)
             r, d = oracle.step(c, s, a)
             where = f"{name} env {e} step {t}"
-            assert np.array_equal(gact[e], a[0]), where
+            assert np.array_equal(gact[e], oracle.sample(c, s, wl.actor_seed, t + 1)[0]), where
             assert np.array_equal(grew[e], r[0]) and gdone[e] == d[0], where
             assert_state_equal({k: v[j:j + 1] for k, v in gst.items()}, s, where)
             assert_obs_equal(gobs[j:j + 1], oracle.observe(c, s), where)
