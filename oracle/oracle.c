@@ -441,7 +441,9 @@ static int legal(const orc_env *s, int p, int cell, int k)
 }
 
 /* Random legal actor (R15): uniform over {pass} + legal (cell, k) listed by
- * cell in row-major order and then k = 1..8. */
+ * cell in row-major order and then k = 1..8.  Player p uses 32-bit draw p of
+ * the stream keyed (actor seed, ACTIONS) with counter prefix (env, step, 0):
+ * one Philox block serves up to eight players. */
 static void sample_env(const orc_env *s, uint64_t seed_act, uint64_t step_idx, uint64_t env_id, int32_t *actions)
 {
     int32_t L[ORC_MAX_CELLS * 8 + 1];
@@ -452,7 +454,7 @@ static void sample_env(const orc_env *s, uint64_t seed_act, uint64_t step_idx, u
         for (int cell = 0; cell < HW; cell++)
             for (int k = 1; k <= 8; k++)
                 if (legal(s, p, cell, k)) L[n++] = cell * 9 + k;
-        uint32_t r = orc_draw(seed_act, D_ACTIONS, env_id, step_idx, (uint64_t)p, 0);
+        uint32_t r = orc_draw(seed_act, D_ACTIONS, env_id, step_idx, 0, (uint64_t)p);
         actions[p] = ((s->alive >> p) & 1) ? L[pick(r, (uint32_t)n)] : 0;
     }
 }
