@@ -57,13 +57,18 @@ _lib = None
 def lib() -> ctypes.CDLL:
     """Load libgenerals.so (torch first, so that one HIP runtime serves both)."""
     global _lib
-    if _lib is not None:
-        return _lib
+    if _lib is None:
+        _lib = load_library(LIB_PATH)
+    return _lib
+
+
+def load_library(path: str) -> ctypes.CDLL:
+    """Open a build of the library at `path` and declare its signatures."""
     import torch  # noqa: F401  -- loads the HIP runtime the library binds to
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
                            "(python -m paper_2606_23348_amd.build)")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp, i32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
     P = ctypes.POINTER
     L.gen_version.argtypes, L.gen_version.restype = [], ctypes.c_int
@@ -82,7 +87,6 @@ def lib() -> ctypes.CDLL:
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
               "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs"):
         getattr(L, f).restype = ctypes.c_int
-    _lib = L
     return L
 
 

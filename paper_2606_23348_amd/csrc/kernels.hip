@@ -11,7 +11,8 @@ namespace gen {
 // ---------------------------------------------------------------- LDS carve-up
 // Per env, S = padded cells per row (multiple of 16):
 //   army  int32 [S] | owner int8 [S] | type uint8 [S] | armyc uint8 [S] + 16
-//   code  uint8 [P*S] + 16            (per player, bits = obs channels 0..6)
+//   code  uint8 [P*S] + 16            (per player, bits = obs channels 0..6;
+//                                      overlays the army row when it fits)
 //   obm   u64 [P][16]                 (cells owned by each player)
 //   vis   u64 [P][16]                 (visible cell bitmaps)
 //   gbm   u64 [3][16] + int32 [8]      (map generator scratch bitmaps, general cells)
@@ -26,7 +27,8 @@ struct Lds {
 
 __host__ __device__ inline uint32_t lds_bytes_for(int S, int P)
 {
-    return (uint32_t)(4 * S + S + S + (S + 16) + (P * S + 16) + 8 * 16 * (2 * P + 3) + 32);
+    const int code = (P * S + 16 <= 4 * S) ? 0 : P * S + 16;   // see carve()
+    return (uint32_t)(4 * S + S + S + (S + 16) + code + 8 * 16 * (2 * P + 3) + 32);
 }
 
 __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
@@ -37,7 +39,14 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
     L.owner = reinterpret_cast<int8_t *>(smem + o); o += g.S;
     L.type = smem + o; o += g.S;
     L.armyc = smem + o; o += g.S + 16;
-    L.code = smem + o; o += g.P * g.S + 16;
+    // The code planes are written only after the last read of the army row
+    // (the state store), so when they fit they reuse its space: less LDS per
+    // env, more waves per CU.
+    if (g.P * g.S + 16 <= 4 * g.S) {
+        L.code = smem;
+    } else {
+        L.code = smem + o; o += g.P * g.S + 16;
+    }
     L.obm = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.vis = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.gbm = reinterpret_cast<uint64_t *>(smem + o);
@@ -196,22 +205,34 @@ __device__ void mapgen_wave(const Lds &L, const Geom &g, const GenParamsDev &prm
 // ---------------------------------------------------------------- moves (Section IV-D)
 __device__ __forceinline__ bool is_ally(int mode, int a, int b) { return mode == MODE_2V2 && a != b && ((a ^ b) & 1) == 0; }
 
-// Apply player i's action on lane 0.  Returns the player whose general was
-// captured (-1 if none); the captured general becomes a castle here.
-__device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int i, int32_t a)
+// Decode one action (on the lane of its player): source and destination
+// cells and the half flag packed as src | dst << 10 | half << 20, or -1 when
+// the code can never be legal (out of range, k = 0, off the grid, into a
+// mountain -- mountains never change during a step).
+__device__ __forceinline__ int decode_action(const Lds &L, const Geom &g, int32_t a)
 {
-    if (!((s.alive >> i) & 1)) return -1;
     if (a < 0 || a >= g.HW * 9) return -1;
     const int src = a / 9, k = a - src * 9;
     if (k == 0) return -1;
     const int dir = (k - 1) & 3;
-    const bool half = k >= 5;
     int r = div_w(src, g), c = src - r * g.W;
     r += dir == 0 ? -1 : dir == 1 ? 1 : 0;
     c += dir == 2 ? -1 : dir == 3 ? 1 : 0;
     if (r < 0 || r >= g.H || c < 0 || c >= g.W) return -1;
     const int dst = r * g.W + c;
-    if (L.type[dst] == MOUNTAIN || L.owner[src] != i) return -1;
+    if (L.type[dst] == MOUNTAIN) return -1;
+    return src | (dst << 10) | ((k >= 5 ? 1 : 0) << 20);
+}
+
+// Apply player i's decoded move on lane 0, re-validating ownership and army
+// at application time (R4/R5).  Returns the player whose general was
+// captured (-1 if none); the captured general becomes a castle here.
+__device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int i, int packed)
+{
+    if (packed < 0 || !((s.alive >> i) & 1)) return -1;
+    const int src = packed & 1023, dst = (packed >> 10) & 1023;
+    const bool half = (packed >> 20) & 1;
+    if (L.owner[src] != i) return -1;
     const int32_t have = L.army[src];
     if (have <= 1) return -1;
     const int32_t m = half ? (have >> 1) : have - 1;
@@ -248,13 +269,14 @@ __device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int 
 // Returns true if a general was captured (the type row then changed).
 __device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_t my_action)
 {
-    bool captured = false;
     const int lane = lane_id();
+    bool captured = false;
+    const int my_move = lane < g.P ? decode_action(L, g, my_action) : -1;
     for (int j = 0; j < g.P; ++j) {
         const int i = (s.turn + j) % g.P;
-        const int32_t a = readlane(my_action, i);
+        const int packed = readlane(my_move, i);
         int victim = -1;
-        if (lane == 0) victim = apply_move(L, g, s, i, a);
+        if (lane == 0) victim = apply_move(L, g, s, i, packed);
         victim = readfirst(victim);
         wave_sync();
         if (victim >= 0) {
@@ -295,6 +317,12 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
     const uint64_t lf_ok = ((pw << 1) | (pprev >> 63)) & ~cm.col0;   // c - 1 passable, same row
     const uint64_t rt_ok = ((pw >> 1) | (pnext << 63)) & ~cm.colL;   // c + 1 passable, same row
     const uint64_t bw = big[w];
+    // one Philox block per env: player p takes 32-bit draw p.  The identity
+    // shuffle keeps the block on the vector unit: as a wave-uniform value the
+    // compiler would run it on the scalar unit, whose long 64-bit multiply
+    // chains cost more wave time than the vector version.
+    uint64_t r0 = shfl64(env_id, lane), r1 = step_idx, r2 = 0, r3 = 0;
+    philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
     for (int p0 = 0; p0 < g.P; p0 += ppr) {
         const int p = p0 + lp;
         const bool valid = lp < ppr && p < g.P;
@@ -309,7 +337,8 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
         const uint32_t before = first > 0 ? below : 0u;
         const uint32_t total = upto - before;
         const uint32_t excl = incl - cnt - before;
-        const uint32_t r = draw32(actor_seed, DOM_ACTIONS, env_id, step_idx, (uint64_t)p, 0u);
+        const uint64_t rw = (p >> 1) == 0 ? r0 : (p >> 1) == 1 ? r1 : (p >> 1) == 2 ? r2 : r3;
+        const uint32_t r = (p & 1) ? (uint32_t)(rw >> 32) : (uint32_t)rw;
         const uint32_t idx = pick(r, 1u + total);
         const bool mine = valid && idx > 0 && excl <= idx - 1 && idx - 1 < excl + cnt;
         if (mine) {
