@@ -388,27 +388,62 @@ __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32
     return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
 }
 
-// Four consecutive obs bytes at byte offset b (b % 4 == 0) of an env block.
-template <int OBSV>
-__device__ __forceinline__ uint32_t obs_dword(const Lds &L, const Geom &g, uint32_t b)
+// Four obs bytes at byte offset b (b % 4 == 0) of an env block whose planes
+// are 4-byte aligned (H*W % 4 == 0): the dword lies inside one plane.
+__device__ __forceinline__ uint32_t obs_dword_a4(const Lds &L, const Geom &g, uint32_t b)
 {
     const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-    if (OBSV == OBS_A4) {
-        const uint32_t cd = *reinterpret_cast<const uint32_t *>(L.code + p * g.S + c);
-        if (ch < 7) return (cd >> ch) & 0x01010101u;
-        return *reinterpret_cast<const uint32_t *>(L.armyc + c) & vismask(cd);
+    const uint32_t cd = *reinterpret_cast<const uint32_t *>(L.code + p * g.S + c);
+    if (ch < 7) return (cd >> ch) & 0x01010101u;
+    return *reinterpret_cast<const uint32_t *>(L.armyc + c) & vismask(cd);
+}
+
+// Unaligned run of N/4 dwords from an LDS byte array starting at byte o:
+// N/4 + 1 aligned dword reads and a byte funnel shift per output dword.
+template <int N, bool ALIGN4>
+__device__ __forceinline__ void lds_run(const uint8_t *base, uint32_t o, uint32_t (&out)[N / 4])
+{
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(base) + (o >> 2);
+    if (ALIGN4) {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) out[i] = w[i];
     } else {
-        if (c + 3 >= (uint32_t)g.HW) {
-            return obs_byte(L, g, b) | (obs_byte(L, g, b + 1) << 8) | (obs_byte(L, g, b + 2) << 16) |
-                   (obs_byte(L, g, b + 3) << 24);
+        uint32_t raw[N / 4 + 1];
+#pragma unroll
+        for (int i = 0; i <= N / 4; ++i) raw[i] = w[i];
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) out[i] = __builtin_amdgcn_alignbyte(raw[i + 1], raw[i], o & 3);
+    }
+}
+
+// N obs bytes (N = 8 or 16) at byte offset b (b % N == 0) of an env block.
+// The chunk index is decoded once; a chunk inside one plane is N consecutive
+// cells of one (player, channel); a chunk across a plane boundary falls back
+// to dwords (4-byte aligned planes) or single bytes.
+template <int N, bool ALIGN4>
+__device__ __forceinline__ void obs_chunk(const Lds &L, const Geom &g, uint32_t b, uint32_t (&out)[N / 4])
+{
+    const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
+    if (c + N <= (uint32_t)g.HW) {
+        uint32_t cd[N / 4];
+        lds_run<N, ALIGN4>(L.code, p * g.S + c, cd);
+        if (ch < 7) {
+#pragma unroll
+            for (int i = 0; i < N / 4; ++i) out[i] = (cd[i] >> ch) & 0x01010101u;
+        } else {
+            uint32_t ac[N / 4];
+            lds_run<N, ALIGN4>(L.armyc, c, ac);
+#pragma unroll
+            for (int i = 0; i < N / 4; ++i) out[i] = ac[i] & vismask(cd[i]);
         }
-        const uint32_t o = p * g.S + c;
-        const uint32_t *cw = reinterpret_cast<const uint32_t *>(L.code);
-        const uint32_t cd = __builtin_amdgcn_alignbyte(cw[(o >> 2) + 1], cw[o >> 2], o & 3);
-        if (ch < 7) return (cd >> ch) & 0x01010101u;
-        const uint32_t *aw = reinterpret_cast<const uint32_t *>(L.armyc);
-        const uint32_t ac = __builtin_amdgcn_alignbyte(aw[(c >> 2) + 1], aw[c >> 2], c & 3);
-        return ac & vismask(cd);
+    } else if (ALIGN4) {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) out[i] = obs_dword_a4(L, g, b + 4 * i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i)
+            out[i] = obs_byte(L, g, b + 4 * i) | (obs_byte(L, g, b + 4 * i + 1) << 8) |
+                     (obs_byte(L, g, b + 4 * i + 2) << 16) | (obs_byte(L, g, b + 4 * i + 3) << 24);
     }
 }
 
@@ -630,20 +665,16 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
         } else if (OBSV == OBS_A4 || OBSV == OBS_A1C16) {
             for (uint32_t k = lane; k < (B >> 4); k += kWave) {
                 const uint32_t b = k << 4;
-                uint4 out;
-                out.x = obs_dword<OBSV>(L, g, b);
-                out.y = obs_dword<OBSV>(L, g, b + 4);
-                out.z = obs_dword<OBSV>(L, g, b + 8);
-                out.w = obs_dword<OBSV>(L, g, b + 12);
-                *reinterpret_cast<uint4 *>(ob + b) = out;
+                uint32_t o[4];
+                obs_chunk<16, OBSV == OBS_A4>(L, g, b, o);
+                *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
             }
         } else {
             for (uint32_t k = lane; k < (B >> 3); k += kWave) {
                 const uint32_t b = k << 3;
-                uint2 out;
-                out.x = obs_dword<OBSV>(L, g, b);
-                out.y = obs_dword<OBSV>(L, g, b + 4);
-                *reinterpret_cast<uint2 *>(ob + b) = out;
+                uint32_t o[2];
+                obs_chunk<8, false>(L, g, b, o);
+                *reinterpret_cast<uint2 *>(ob + b) = make_uint2(o[0], o[1]);
             }
         }
     }
