@@ -97,7 +97,8 @@ typedef struct gen_state {
     gen_params params;
     /* Device buffer layout (bytes from d_buf), struct-of-arrays, env-major:
      *   scalars [n_envs] 32-byte records {int32 turn; uint32 episode;
-     *           uint8 alive_mask; uint8 finished; uint8 pad[6]; int16 gpos[8]; }
+     *           uint8 alive_mask; uint8 finished; uint8 pad[2]; uint32 tick;
+     *           int16 gpos[8]; }
      *   owner   int8  [n_envs][stride]  (-1 neutral)
      *   type    uint8 [n_envs][stride]
      *   army    int32 [n_envs][stride]
@@ -192,6 +193,74 @@ int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
  * army, gpos outside the grid, alive bits beyond P, negative turn. */
 int gen_get_state(const gen_state *st, gen_host_state *h, void *stream);
 int gen_set_state(const gen_state *st, const gen_host_state *h, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched pool: envs of different shapes and modes stepped by one launch.
+ * Each env keeps its own shape (3..32 per side), mode, player count and
+ * generator settings; the state lives in one caller-provided device buffer
+ * (layout private to the library), observations, actions and rewards in
+ * ragged caller buffers at the offsets gen_pool_offsets reports.  The random
+ * actor of a pool draws with each env's own step counter (0 at reset, +1
+ * per step) as its step index, so a captured graph can be replayed any
+ * number of times and keeps drawing fresh actions.
+ * ---------------------------------------------------------------------- */
+typedef struct gen_env_spec {
+    int32_t H, W, mode, n_players;        /* n_players: FFA only (2..8) */
+    int32_t cities_min, cities_max;       /* <= 255 */
+    int32_t min_general_dist;             /* <= 255 */
+    int32_t reserved;                     /* must be zero */
+} gen_env_spec;
+
+typedef struct gen_pool gen_pool;        /* opaque host object; owns no device memory */
+
+typedef struct gen_pool_info {
+    int32_t n_envs;
+    int32_t max_cells;          /* largest H*W in the pool */
+    uint64_t state_bytes;       /* device state buffer to pass to gen_pool_reset */
+    uint64_t obs_bytes;         /* ragged observation buffer (each env block 16-byte aligned) */
+    uint64_t n_actions;         /* int32 entries of the ragged actions and rewards buffers (sum of P) */
+} gen_pool_info;
+
+/* Packing of envs onto the GPU (chosen by the autotuner):
+ *   waves_per_group 1, 2 or 4 envs (one wave each) per workgroup;
+ *   grid            0 = one wave per env, else that many workgroups whose
+ *                   waves stride over the work list;
+ *   order           0 = env id order, 1 = largest envs (P*H*W) first. */
+typedef struct gen_pool_tuning {
+    int32_t waves_per_group, grid, order, reserved;
+} gen_pool_tuning;
+
+/* Plan a pool of n_envs envs described by h_specs[n_envs] (host).  `common`
+ * supplies the mountain threshold, city armies, auto_reset and pregrow
+ * (NULL: defaults); its city counts, spawn distance and n_players are
+ * ignored in favour of each spec. */
+int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
+                    const gen_params *common, gen_pool **out);
+int gen_pool_destroy(gen_pool *pool);
+int gen_pool_query(const gen_pool *pool, gen_pool_info *out);
+/* Byte offset of each env's observation block and index of its first action
+ * (host arrays of n_envs entries; either may be NULL). */
+int gen_pool_offsets(const gen_pool *pool, uint64_t *h_obs_off, uint32_t *h_act_off);
+int gen_pool_get_tuning(const gen_pool *pool, gen_pool_tuning *out);
+/* Takes effect at the next launch (uploads the work list if the pool is bound;
+ * blocking on `stream`).  Results never depend on the packing. */
+int gen_pool_set_tuning(gen_pool *pool, const gen_pool_tuning *tuning, void *stream);
+/* Bind the state buffer (>= state_bytes, 256-byte aligned), generate every
+ * env's first map, write observations (d_obs nullable) and, if d_actions is
+ * not NULL, the random actor's actions for step 0. */
+int gen_pool_reset(gen_pool *pool, void *d_state, uint64_t state_bytes, uint8_t *d_obs, int32_t *d_actions,
+                   uint64_t actor_seed, void *stream);
+/* One step of every env.  actor != 0: afterwards draw the next actions into
+ * d_actions with the random actor (fused, same launch). */
+int gen_pool_step(gen_pool *pool, int32_t *d_actions, int32_t actor, uint64_t actor_seed, uint8_t *d_obs,
+                  int32_t *d_rewards, uint8_t *d_dones, void *stream);
+/* Capture k_steps fused steps (actor on) on `stream` (not the null stream)
+ * into a HIP graph held by the pool; replay it with gen_pool_replay. */
+int gen_pool_capture(gen_pool *pool, int32_t k_steps, int32_t *d_actions, uint64_t actor_seed, uint8_t *d_obs,
+                     int32_t *d_rewards, uint8_t *d_dones, void *stream);
+int gen_pool_replay(gen_pool *pool, void *stream);
+/* Blocking copy of one env in the public host format (one row of H*W cells). */
+int gen_pool_get_env(const gen_pool *pool, int32_t env, gen_host_state *h, void *stream);
 
 /* Blocking copy of selected envs only: env h_env_ids[i] (0 <= id < n_envs)
  * goes to row i of each host array, which therefore hold n_ids rows.  For

@@ -51,6 +51,20 @@ class gen_host_state(ctypes.Structure):
                 ("owner", "army", "type", "turn", "episode", "alive", "finished", "gpos")]
 
 
+class gen_env_spec(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("H", "W", "mode", "n_players", "cities_min", "cities_max", "min_general_dist", "reserved")]
+
+
+class gen_pool_info(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("max_cells", ctypes.c_int32), ("state_bytes", ctypes.c_uint64),
+                ("obs_bytes", ctypes.c_uint64), ("n_actions", ctypes.c_uint64)]
+
+
+class gen_pool_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("waves_per_group", "grid", "order", "reserved")]
+
+
 _lib = None
 
 
@@ -84,8 +98,22 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_get_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_set_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_get_envs.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
+    L.gen_pool_create.argtypes = [u64, u64, i32, vp, P(gen_params), P(vp)]
+    L.gen_pool_destroy.argtypes = [vp]
+    L.gen_pool_query.argtypes = [vp, P(gen_pool_info)]
+    L.gen_pool_offsets.argtypes = [vp, vp, vp]
+    L.gen_pool_get_tuning.argtypes = [vp, P(gen_pool_tuning)]
+    L.gen_pool_set_tuning.argtypes = [vp, P(gen_pool_tuning), vp]
+    L.gen_pool_reset.argtypes = [vp, vp, u64, vp, vp, u64, vp]
+    L.gen_pool_step.argtypes = [vp, vp, i32, u64, vp, vp, vp, vp]
+    L.gen_pool_capture.argtypes = [vp, i32, vp, u64, vp, vp, vp, vp]
+    L.gen_pool_replay.argtypes = [vp, vp]
+    L.gen_pool_get_env.argtypes = [vp, i32, P(gen_host_state), vp]
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
-              "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs"):
+              "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
+              "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
+              "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
+              "gen_pool_get_env"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -260,3 +288,91 @@ class Batch:
 
     def set_state(self, h: dict, stream=None):
         gen_set_state(self.st, h, stream)
+
+
+# ---------------------------------------------------------------------------- batched pool
+SPEC_FIELDS = ("H", "W", "mode", "P", "cities_min", "cities_max", "min_general_dist")
+
+
+def gen_pool_create(seed: int, env_base: int, specs: dict, common: gen_params | None = None) -> ctypes.c_void_p:
+    """specs: dict of equal-length integer arrays with keys SPEC_FIELDS."""
+    n = len(specs["H"])
+    arr = (gen_env_spec * n)()
+    for i in range(n):
+        arr[i] = gen_env_spec(int(specs["H"][i]), int(specs["W"][i]), int(specs["mode"][i]), int(specs["P"][i]),
+                              int(specs["cities_min"][i]), int(specs["cities_max"][i]),
+                              int(specs["min_general_dist"][i]), 0)
+    h = ctypes.c_void_p()
+    _check(lib().gen_pool_create(seed, env_base, n, arr, ctypes.byref(common) if common else None,
+                                 ctypes.byref(h)))
+    return h
+
+
+class Pool:
+    """Device buffers of one batched pool (torch allocates, the library
+    computes).  Every method is one library call."""
+
+    def __init__(self, specs: dict, common: gen_params | None = None, seed: int = 0, env_base: int = 0,
+                 device: str = "cuda", with_obs: bool = True):
+        import torch
+        self.specs = {k: np.asarray(specs[k]) for k in SPEC_FIELDS}
+        self.handle = gen_pool_create(seed, env_base, self.specs, common)
+        info = gen_pool_info()
+        _check(lib().gen_pool_query(self.handle, ctypes.byref(info)))
+        self.n = info.n_envs
+        self.info = info
+        self.obs_off = np.zeros(self.n, np.uint64)
+        self.act_off = np.zeros(self.n, np.uint32)
+        _check(lib().gen_pool_offsets(self.handle, self.obs_off.ctypes.data, self.act_off.ctypes.data))
+        self.buf = torch.empty(info.state_bytes, dtype=torch.uint8, device=device)
+        self.obs = torch.empty(max(info.obs_bytes, 16), dtype=torch.uint8, device=device) if with_obs else None
+        self.actions = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
+        self.rewards = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
+        self.dones = torch.zeros(self.n, dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gen_pool_destroy(self.handle)
+            self.handle = None
+
+    def reset(self, actor_seed: int | None = None, stream=None):
+        _check(lib().gen_pool_reset(self.handle, _ptr(self.buf), self.buf.numel(), _ptr(self.obs),
+                                    _ptr(self.actions) if actor_seed is not None else None,
+                                    actor_seed or 0, _stream(stream)))
+
+    def step(self, actor_seed: int | None = None, stream=None):
+        _check(lib().gen_pool_step(self.handle, _ptr(self.actions), 1 if actor_seed is not None else 0,
+                                   actor_seed or 0, _ptr(self.obs), _ptr(self.rewards), _ptr(self.dones),
+                                   _stream(stream)))
+
+    def capture(self, k_steps: int, actor_seed: int, stream):
+        _check(lib().gen_pool_capture(self.handle, k_steps, _ptr(self.actions), actor_seed, _ptr(self.obs),
+                                      _ptr(self.rewards), _ptr(self.dones), _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().gen_pool_replay(self.handle, _stream(stream)))
+
+    def tuning(self) -> dict:
+        t = gen_pool_tuning()
+        _check(lib().gen_pool_get_tuning(self.handle, ctypes.byref(t)))
+        return {"waves_per_group": t.waves_per_group, "grid": t.grid, "order": t.order}
+
+    def set_tuning(self, waves_per_group: int = 1, grid: int = 0, order: int = 0, stream=None):
+        t = gen_pool_tuning(waves_per_group, grid, order, 0)
+        _check(lib().gen_pool_set_tuning(self.handle, ctypes.byref(t), _stream(stream)))
+
+    def get_env(self, e: int, stream=None) -> dict:
+        HW = int(self.specs["H"][e]) * int(self.specs["W"][e])
+        h = _host_arrays(1, HW, int(self.specs["P"][e]))
+        hs = _host_struct(h)
+        _check(lib().gen_pool_get_env(self.handle, e, ctypes.byref(hs), _stream(stream)))
+        return h
+
+    def env_obs(self, e: int):
+        H, W, P = (int(self.specs[k][e]) for k in ("H", "W", "P"))
+        o = int(self.obs_off[e])
+        return self.obs[o:o + P * 8 * H * W].view(P, 8, H, W)
+
+    def env_slice(self, e: int):
+        a = int(self.act_off[e])
+        return slice(a, a + int(self.specs["P"][e]))

@@ -2,10 +2,12 @@
 // device layout, launches, host-format copies and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -76,6 +78,7 @@ gen::Geom geom_of(const gen_state &st)
     g.NW = (g.HW + 63) / 64;
     g.magic_w = (uint32_t)(((1u << 20) + (uint32_t)st.W - 1) / (uint32_t)st.W);
     g.magic_hw = (uint32_t)(((uint64_t(1) << 32) + (uint64_t)g.HW - 1) / (uint64_t)g.HW);
+    g.obsv = gen::obs_variant(g.HW, g.P);
     return g;
 }
 
@@ -130,6 +133,72 @@ int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
     const uint64_t B = (uint64_t)st.n_players * 8 * st.H * st.W;
     const uintptr_t need = (B % 16 == 0) ? 16 : 8;
     if (!aligned(d_obs, need)) return fail(GEN_EINVAL, "d_obs must be %u-byte aligned", (unsigned)need);
+    return GEN_OK;
+}
+
+}  // namespace
+
+// Host plan of a batched pool (see generals.h).
+struct gen_pool {
+    uint64_t seed = 0, env_base = 0;
+    int32_t n = 0;
+    gen_params common{};
+    std::vector<gen::PoolDesc> desc;
+    std::vector<uint64_t> work;           // P*H*W per env, for the work order
+    std::vector<uint32_t> order;
+    uint64_t off_scalars = 0, off_desc = 0, off_order = 0, off_owner = 0, off_type = 0, off_army = 0;
+    uint64_t state_bytes = 0, obs_bytes = 0, n_actions = 0;
+    uint32_t lds_per_wave = 0;
+    int32_t max_cells = 0;
+    gen_pool_tuning tuning{1, 0, 0, 0};
+    void *d_state = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void pool_make_order(gen_pool &pl)
+{
+    pl.order.resize((size_t)pl.n);
+    for (int32_t i = 0; i < pl.n; ++i) pl.order[(size_t)i] = (uint32_t)i;
+    if (pl.tuning.order == 1) {
+        std::stable_sort(pl.order.begin(), pl.order.end(),
+                         [&](uint32_t a, uint32_t b) { return pl.work[a] > pl.work[b]; });
+    }
+}
+
+gen::PoolArgs pool_args(const gen_pool &pl)
+{
+    gen::PoolArgs a{};
+    a.prm = prm_of(pl.common);
+    a.seed = pl.seed;
+    a.env_base = pl.env_base;
+    a.n_envs = (uint32_t)pl.n;
+    a.wpg = (uint32_t)pl.tuning.waves_per_group;
+    a.lds_per_wave = pl.lds_per_wave;
+    uint8_t *base = static_cast<uint8_t *>(pl.d_state);
+    a.desc = reinterpret_cast<const gen::PoolDesc *>(base + pl.off_desc);
+    a.order = reinterpret_cast<const uint32_t *>(base + pl.off_order);
+    a.sc = reinterpret_cast<gen::EnvScalars *>(base + pl.off_scalars);
+    a.owner = reinterpret_cast<int8_t *>(base + pl.off_owner);
+    a.type = base + pl.off_type;
+    a.army = reinterpret_cast<int32_t *>(base + pl.off_army);
+    return a;
+}
+
+int pool_upload_order(gen_pool &pl, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(pl.d_state) + pl.off_order, pl.order.data(),
+                                  pl.order.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GEN_OK : hip_fail(e, "pool work-list upload");
+}
+
+int check_bound(const gen_pool *pl)
+{
+    if (pl == nullptr) return fail(GEN_EINVAL, "pool is NULL");
+    if (pl->d_state == nullptr) return fail(GEN_EINVAL, "pool has no state buffer (call gen_pool_reset)");
     return GEN_OK;
 }
 
@@ -370,6 +439,263 @@ int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, g
         h->finished[i] = sc[i].finished;
         for (int p = 0; p < P; ++p) h->gpos[(size_t)i * P + p] = sc[i].gpos[p];
     }
+    return ok();
+}
+
+int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
+                    const gen_params *common, gen_pool **out)
+{
+    if (out == nullptr || h_specs == nullptr) return fail(GEN_EINVAL, "out and h_specs are required");
+    *out = nullptr;
+    if (n_envs < 1) return fail(GEN_EINVAL, "n_envs %d must be positive", n_envs);
+    gen_params cp;
+    if (common) cp = *common;
+    else gen_default_params(GEN_1V1, 0, &cp);
+    gen_pool *pl = new (std::nothrow) gen_pool();
+    if (pl == nullptr) return fail(GEN_ENOMEM, "host allocation failed");
+    pl->seed = seed;
+    pl->env_base = env_base;
+    pl->n = n_envs;
+    pl->common = cp;
+    pl->desc.resize((size_t)n_envs);
+    pl->work.resize((size_t)n_envs);
+    uint64_t cells = 0, obs16 = 0, acts = 0;
+    int max_s = 16, max_p = 2;
+    for (int32_t i = 0; i < n_envs; ++i) {
+        const gen_env_spec &sp = h_specs[i];
+        gen_params p = cp;
+        p.n_players = sp.n_players;
+        p.cities_min = sp.cities_min;
+        p.cities_max = sp.cities_max;
+        p.min_general_dist = sp.min_general_dist;
+        gen_state st;
+        if (sp.reserved != 0 || gen_layout(1, sp.H, sp.W, sp.mode, &p, seed, &st) != GEN_OK) {
+            const std::string why = g_last_error;
+            delete pl;
+            return fail(GEN_EINVAL, "env spec %d: %s", i, sp.reserved != 0 ? "reserved must be zero" : why.c_str());
+        }
+        if (sp.cities_max > 255 || sp.min_general_dist > 255) {
+            delete pl;
+            return fail(GEN_EINVAL, "env spec %d: cities_max and min_general_dist must be <= 255", i);
+        }
+        const gen::Geom g = geom_of(st);
+        gen::PoolDesc &d = pl->desc[(size_t)i];
+        d.cell_off = (uint32_t)cells;
+        d.obs_off16 = (uint32_t)obs16;
+        d.act_off = (uint32_t)acts;
+        d.magic_w = g.magic_w;
+        d.magic_hw = g.magic_hw;
+        d.H = (uint8_t)sp.H;
+        d.W = (uint8_t)sp.W;
+        d.mode = (uint8_t)sp.mode;
+        d.P = (uint8_t)st.n_players;
+        d.cmin = (uint8_t)sp.cities_min;
+        d.cmax = (uint8_t)sp.cities_max;
+        d.dmin = (uint8_t)sp.min_general_dist;
+        d.obsv = (uint8_t)g.obsv;
+        d.reserved = 0;
+        cells += (uint64_t)st.stride;
+        obs16 += ((uint64_t)st.n_players * 8 * sp.H * sp.W + 15) / 16;
+        acts += (uint64_t)st.n_players;
+        pl->work[(size_t)i] = (uint64_t)st.n_players * sp.H * sp.W;
+        if (st.stride > max_s) max_s = st.stride;
+        if (st.n_players > max_p) max_p = st.n_players;
+        if (sp.H * sp.W > pl->max_cells) pl->max_cells = sp.H * sp.W;
+    }
+    if (cells > 0xFFFFFFFFull || obs16 > 0xFFFFFFFFull) {
+        delete pl;
+        return fail(GEN_EINVAL, "pool too large for 32-bit offsets");
+    }
+    const uint64_t E = (uint64_t)n_envs;
+    pl->off_scalars = 0;
+    pl->off_desc = align256(E * sizeof(gen::EnvScalars));
+    pl->off_order = pl->off_desc + align256(E * sizeof(gen::PoolDesc));
+    pl->off_owner = pl->off_order + align256(E * sizeof(uint32_t));
+    pl->off_type = pl->off_owner + align256(cells);
+    pl->off_army = pl->off_type + align256(cells);
+    pl->state_bytes = pl->off_army + align256(cells * 4);
+    pl->obs_bytes = obs16 * 16;
+    pl->n_actions = acts;
+    pl->lds_per_wave = (gen::lds_bytes_for(max_s, max_p) + 15) & ~15u;
+    pool_make_order(*pl);
+    *out = pl;
+    return ok();
+}
+
+int gen_pool_destroy(gen_pool *pool)
+{
+    if (pool == nullptr) return ok();
+    if (pool->exec) (void)hipGraphExecDestroy(pool->exec);
+    if (pool->graph) (void)hipGraphDestroy(pool->graph);
+    delete pool;
+    return ok();
+}
+
+int gen_pool_query(const gen_pool *pool, gen_pool_info *out)
+{
+    if (pool == nullptr || out == nullptr) return fail(GEN_EINVAL, "pool and out are required");
+    out->n_envs = pool->n;
+    out->max_cells = pool->max_cells;
+    out->state_bytes = pool->state_bytes;
+    out->obs_bytes = pool->obs_bytes;
+    out->n_actions = pool->n_actions;
+    return ok();
+}
+
+int gen_pool_offsets(const gen_pool *pool, uint64_t *h_obs_off, uint32_t *h_act_off)
+{
+    if (pool == nullptr) return fail(GEN_EINVAL, "pool is NULL");
+    for (int32_t i = 0; i < pool->n; ++i) {
+        if (h_obs_off) h_obs_off[i] = (uint64_t)pool->desc[(size_t)i].obs_off16 * 16;
+        if (h_act_off) h_act_off[i] = pool->desc[(size_t)i].act_off;
+    }
+    return ok();
+}
+
+int gen_pool_get_tuning(const gen_pool *pool, gen_pool_tuning *out)
+{
+    if (pool == nullptr || out == nullptr) return fail(GEN_EINVAL, "pool and out are required");
+    *out = pool->tuning;
+    return ok();
+}
+
+int gen_pool_set_tuning(gen_pool *pool, const gen_pool_tuning *t, void *stream)
+{
+    if (pool == nullptr || t == nullptr) return fail(GEN_EINVAL, "pool and tuning are required");
+    if (t->waves_per_group != 1 && t->waves_per_group != 2 && t->waves_per_group != 4)
+        return fail(GEN_EINVAL, "waves_per_group must be 1, 2 or 4");
+    if (t->grid < 0 || (t->order != 0 && t->order != 1) || t->reserved != 0)
+        return fail(GEN_EINVAL, "grid must be >= 0, order 0 or 1, reserved 0");
+    if ((uint64_t)pool->lds_per_wave * (uint64_t)t->waves_per_group > 65536)
+        return fail(GEN_EINVAL, "%d waves per group need more than 64 KiB of LDS", t->waves_per_group);
+    const bool reorder = t->order != pool->tuning.order;
+    pool->tuning = *t;
+    if (reorder) {
+        pool_make_order(*pool);
+        if (pool->d_state) return pool_upload_order(*pool, static_cast<hipStream_t>(stream)) == GEN_OK ? ok() : GEN_EHIP;
+    }
+    return ok();
+}
+
+int gen_pool_reset(gen_pool *pool, void *d_state, uint64_t state_bytes, uint8_t *d_obs, int32_t *d_actions,
+                   uint64_t actor_seed, void *stream)
+{
+    if (pool == nullptr) return fail(GEN_EINVAL, "pool is NULL");
+    if (d_state == nullptr || !aligned(d_state, 256)) return fail(GEN_EINVAL, "d_state must be 256-byte aligned");
+    if (state_bytes < pool->state_bytes)
+        return fail(GEN_ENOMEM, "state buffer holds %llu bytes, pool needs %llu", (unsigned long long)state_bytes,
+                    (unsigned long long)pool->state_bytes);
+    if ((d_obs && !aligned(d_obs, 16)) || (d_actions && !aligned(d_actions, 4)))
+        return fail(GEN_EINVAL, "d_obs must be 16-byte and d_actions 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pool->d_state = d_state;
+    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(d_state) + pool->off_desc, pool->desc.data(),
+                                  pool->desc.size() * sizeof(gen::PoolDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pool descriptor upload");
+    if (pool_upload_order(*pool, s) != GEN_OK) return GEN_EHIP;
+    gen::PoolArgs a = pool_args(*pool);
+    a.obs = d_obs;
+    a.actions = d_actions;
+    a.actor_seed = actor_seed;
+    e = gen::launch_pool(a, 1 /* reset */, d_actions != nullptr, (uint32_t)pool->tuning.grid, s);
+    if (e != hipSuccess) return hip_fail(e, "pool reset launch");
+    return ok();
+}
+
+int gen_pool_step(gen_pool *pool, int32_t *d_actions, int32_t actor, uint64_t actor_seed, uint8_t *d_obs,
+                  int32_t *d_rewards, uint8_t *d_dones, void *stream)
+{
+    if (check_bound(pool) != GEN_OK) return GEN_EINVAL;
+    if (d_actions == nullptr || d_rewards == nullptr || d_dones == nullptr)
+        return fail(GEN_EINVAL, "d_actions, d_rewards and d_dones are required");
+    if ((d_obs && !aligned(d_obs, 16)) || !aligned(d_actions, 4) || !aligned(d_rewards, 4))
+        return fail(GEN_EINVAL, "misaligned obs, action or reward pointer");
+    gen::PoolArgs a = pool_args(*pool);
+    a.obs = d_obs;
+    a.actions = d_actions;
+    a.rewards = d_rewards;
+    a.dones = d_dones;
+    a.actor_seed = actor_seed;
+    hipError_t e = gen::launch_pool(a, 0 /* step */, actor != 0, (uint32_t)pool->tuning.grid,
+                                    static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pool step launch");
+    return ok();
+}
+
+int gen_pool_capture(gen_pool *pool, int32_t k_steps, int32_t *d_actions, uint64_t actor_seed, uint8_t *d_obs,
+                     int32_t *d_rewards, uint8_t *d_dones, void *stream)
+{
+    if (check_bound(pool) != GEN_OK) return GEN_EINVAL;
+    if (stream == nullptr) return fail(GEN_EINVAL, "capture needs a non-null stream");
+    if (k_steps < 1 || k_steps > 100000) return fail(GEN_EINVAL, "k_steps %d outside [1, 100000]", k_steps);
+    if (d_actions == nullptr || d_rewards == nullptr || d_dones == nullptr)
+        return fail(GEN_EINVAL, "d_actions, d_rewards and d_dones are required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (pool->exec) { (void)hipGraphExecDestroy(pool->exec); pool->exec = nullptr; }
+    if (pool->graph) { (void)hipGraphDestroy(pool->graph); pool->graph = nullptr; }
+    gen::PoolArgs a = pool_args(*pool);
+    a.obs = d_obs;
+    a.actions = d_actions;
+    a.rewards = d_rewards;
+    a.dones = d_dones;
+    a.actor_seed = actor_seed;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    for (int32_t k = 0; k < k_steps && e == hipSuccess; ++k) e = gen::launch_pool(a, 0, true, (uint32_t)pool->tuning.grid, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(e != hipSuccess ? e : e2, "capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "graph instantiate");
+    }
+    pool->graph = graph;
+    pool->exec = exec;
+    return ok();
+}
+
+int gen_pool_replay(gen_pool *pool, void *stream)
+{
+    if (check_bound(pool) != GEN_OK) return GEN_EINVAL;
+    if (pool->exec == nullptr) return fail(GEN_EINVAL, "no captured graph (call gen_pool_capture)");
+    hipError_t e = hipGraphLaunch(pool->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return ok();
+}
+
+int gen_pool_get_env(const gen_pool *pool, int32_t env, gen_host_state *h, void *stream)
+{
+    if (check_bound(pool) != GEN_OK) return GEN_EINVAL;
+    if (env < 0 || env >= pool->n) return fail(GEN_EINVAL, "env %d outside [0, %d)", env, pool->n);
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    const gen::PoolDesc &d = pool->desc[(size_t)env];
+    const int HW = d.H * d.W;
+    const uint8_t *base = static_cast<const uint8_t *>(pool->d_state);
+    gen::EnvScalars sc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(h->owner, base + pool->off_owner + d.cell_off, HW, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->type, base + pool->off_type + d.cell_off, HW, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->army, base + pool->off_army + (uint64_t)d.cell_off * 4, (size_t)HW * 4,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&sc, base + pool->off_scalars + (uint64_t)env * sizeof(sc), sizeof(sc),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pool env download");
+    h->turn[0] = sc.turn;
+    h->episode[0] = sc.episode;
+    h->alive[0] = sc.alive;
+    h->finished[0] = sc.finished;
+    for (int p = 0; p < d.P; ++p) h->gpos[p] = sc.gpos[p];
     return ok();
 }
 

@@ -22,7 +22,8 @@ struct __align__(16) EnvScalars {
     uint32_t episode;
     uint8_t alive;
     uint8_t finished;
-    uint8_t pad[6];
+    uint8_t pad[2];
+    uint32_t tick;          // steps applied since reset (batched pool: the actor's step index)
     int16_t gpos[8];
 };
 static_assert(sizeof(EnvScalars) == 32, "scalar record is 32 bytes");
@@ -32,7 +33,20 @@ struct Geom {
     int H, W, HW, S, P, mode, NW;
     uint32_t magic_w;    // ceil(2^20 / W): c / W == (c * magic_w) >> 20 for c < 1024
     uint32_t magic_hw;   // ceil(2^32 / HW): b / HW == (b * magic_hw) >> 32 for b < 65536
+    int obsv;            // observation writer variant (plane alignment)
 };
+
+// Per-env descriptor of a batched pool (32 bytes, device resident).
+struct PoolDesc {
+    uint32_t cell_off;   // first cell of the env in the owner/type/army arrays (multiple of 16)
+    uint32_t obs_off16;  // offset of the env's observation block, in 16-byte units
+    uint32_t act_off;    // first int32 of the env's actions and rewards
+    uint32_t magic_w, magic_hw;
+    uint8_t H, W, mode, P;
+    uint8_t cmin, cmax, dmin, obsv;
+    uint32_t reserved;
+};
+static_assert(sizeof(PoolDesc) == 32, "pool descriptor is 32 bytes");
 
 struct GenParamsDev {
     uint32_t thresh;

@@ -25,7 +25,7 @@ struct Lds {
     uint64_t *obm, *vis, *gbm;
 };
 
-__host__ __device__ inline uint32_t lds_bytes_for(int S, int P)
+uint32_t lds_bytes_for(int S, int P)
 {
     const int code = (P * S + 16 <= 4 * S) ? 0 : P * S + 16;   // see carve()
     return (uint32_t)(4 * S + S + S + (S + 16) + code + 8 * 16 * (2 * P + 3) + 32);
@@ -373,7 +373,7 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
 
 // ---------------------------------------------------------------- fused env kernel
 enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
-enum { OBS_A16 = 0, OBS_A4 = 1, OBS_A1C16 = 2, OBS_A1C8 = 3 };
+enum { OBS_A16 = 0, OBS_A4 = 1, OBS_A1C16 = 2, OBS_A1C8 = 3, OBS_RUNTIME = -1 };
 
 __device__ __forceinline__ uint32_t vismask(uint32_t code4)
 {
@@ -440,47 +440,71 @@ __device__ __forceinline__ void obs_chunk(const Lds &L, const Geom &g, uint32_t 
 #pragma unroll
         for (int i = 0; i < N / 4; ++i) out[i] = obs_dword_a4(L, g, b + 4 * i);
     } else {
+        // rare (a chunk across a plane boundary): byte by byte, kept rolled
 #pragma unroll
-        for (int i = 0; i < N / 4; ++i)
-            out[i] = obs_byte(L, g, b + 4 * i) | (obs_byte(L, g, b + 4 * i + 1) << 8) |
-                     (obs_byte(L, g, b + 4 * i + 2) << 16) | (obs_byte(L, g, b + 4 * i + 3) << 24);
+        for (int i = 0; i < N / 4; ++i) {
+            uint32_t v = 0;
+#pragma nounroll
+            for (int j = 0; j < 4; ++j) v |= obs_byte(L, g, b + 4 * i + j) << (8 * j);
+            out[i] = v;
+        }
     }
 }
 
+// Per-env inputs and outputs of one step (pointers into this env's rows).
+struct EnvIO {
+    EnvScalars *sc;
+    int8_t *owner;
+    uint8_t *type;
+    int32_t *army;
+    const int32_t *actions;     // P actions of this step
+    int32_t *next_actions;      // fused actor output (ACT)
+    int32_t *rewards;
+    uint8_t *done;
+    uint8_t *obs;               // this env's [P][8][H][W] block, nullptr = no observation
+    int32_t *land;              // scoreboard (SB)
+    int64_t *army_tot;
+    uint64_t env_id;            // global id (keys every draw)
+    uint64_t actor_step;        // actor step index when the tick is not used
+    bool use_tick;              // keep the per-env step counter; the actor draws with it
+};
+
+// One environment step (or reset / observation) on one wave.  OBSV selects
+// the observation writer at compile time, or at run time from g.obsv when
+// OBSV == OBS_RUNTIME (mixed shapes in one launch).
 template <int KIND, int OBSV, bool SB, bool ACT>
-__global__ __launch_bounds__(64) void k_env(EnvArgs a)
+__device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const GenParamsDev &prm, uint64_t seed,
+                                         uint64_t actor_seed, const EnvIO &io)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
     const int lane = lane_id();
-    const int e = blockIdx.x;
-    const Geom g = a.g;
     const Lds L = carve(smem, g);
-    const uint64_t env_id = a.env_base + (uint64_t)e;
-    const size_t cell0 = (size_t)e * g.S;
+    const uint64_t env_id = io.env_id;
 
     EnvScalars s;
     bool write_type = false, grow2 = false, grow50 = false, done = false;
     uint32_t win = 0, lose = 0;
 
     if (KIND == K_RESET) {
-        mapgen_wave(L, g, a.prm, a.seed, env_id, 0u, s);
+        mapgen_wave(L, g, prm, seed, env_id, 0u, s);
+        s.tick = 0;
         write_type = true;
     } else {
-        s = a.sc[e];
+        s = *io.sc;
         // state HBM -> LDS, 16-byte loads
         const int n16 = g.S >> 4;
-        const uint4 *go = reinterpret_cast<const uint4 *>(a.owner + cell0);
-        const uint4 *gt = reinterpret_cast<const uint4 *>(a.type + cell0);
-        const uint4 *ga = reinterpret_cast<const uint4 *>(a.army + cell0);
+        const uint4 *go = reinterpret_cast<const uint4 *>(io.owner);
+        const uint4 *gt = reinterpret_cast<const uint4 *>(io.type);
+        const uint4 *ga = reinterpret_cast<const uint4 *>(io.army);
         for (int i = lane; i < n16; i += kWave) {
             reinterpret_cast<uint4 *>(L.owner)[i] = go[i];
             reinterpret_cast<uint4 *>(L.type)[i] = gt[i];
         }
         for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(L.army)[i] = ga[i];
         int32_t act = 0;
-        if (KIND == K_STEP && lane < g.P) act = a.actions[(size_t)e * g.P + lane];
+        if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
         wave_sync();
         if (KIND == K_STEP) {
+            if (io.use_tick) s.tick += 1;
             if (!s.finished) {
                 const uint32_t alive0 = s.alive;
                 write_type = resolve_moves(L, g, s, act);
@@ -502,8 +526,8 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
                     if (__popc(alive) == 1) { done = true; win = alive; }
                 }
                 if (done) {
-                    if (a.prm.auto_reset) {
-                        mapgen_wave(L, g, a.prm, a.seed, env_id, s.episode + 1u, s);
+                    if (prm.auto_reset) {
+                        mapgen_wave(L, g, prm, seed, env_id, s.episode + 1u, s);
                         write_type = true;
                         grow2 = grow50 = false;
                     } else {
@@ -526,9 +550,9 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
     }
     {
         const int nq = g.S >> 2;
-        uint32_t *go = reinterpret_cast<uint32_t *>(a.owner + cell0);
-        uint32_t *gt = reinterpret_cast<uint32_t *>(a.type + cell0);
-        int4 *ga = reinterpret_cast<int4 *>(a.army + cell0);
+        uint32_t *go = reinterpret_cast<uint32_t *>(io.owner);
+        uint32_t *gt = reinterpret_cast<uint32_t *>(io.type);
+        int4 *ga = reinterpret_cast<int4 *>(io.army);
         for (int q = lane; q < nq; q += kWave) {
             const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
             const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
@@ -567,8 +591,8 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
             lp = (int)wave_sum_u32((uint32_t)lp);
             ap = wave_sum_i64(ap);
             if (lane == 0) {
-                a.land[(size_t)e * g.P + p] = lp;
-                a.army_tot[(size_t)e * g.P + p] = ap;
+                io.land[p] = lp;
+                io.army_tot[p] = ap;
             }
         }
     }
@@ -639,10 +663,27 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
     wave_sync();
 
     // ---- observation stream: uint8 [P][8][H][W] per env, 16- or 8-byte stores
-    if (a.obs != nullptr) {
+    if (io.obs != nullptr) {
         const uint32_t B = (uint32_t)(g.P * 8 * g.HW);
-        uint8_t *ob = a.obs + (size_t)e * B;
-        if (OBSV == OBS_A16) {
+        uint8_t *ob = io.obs;
+        if (OBSV == OBS_RUNTIME) {
+            // mixed shapes in one launch: one generic writer for every plane alignment
+            if ((B & 15u) == 0) {
+                for (uint32_t k = lane; k < (B >> 4); k += kWave) {
+                    const uint32_t b = k << 4;
+                    uint32_t o[4];
+                    obs_chunk<16, false>(L, g, b, o);
+                    *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
+                }
+            } else {
+                for (uint32_t k = lane; k < (B >> 3); k += kWave) {
+                    const uint32_t b = k << 3;
+                    uint32_t o[2];
+                    obs_chunk<8, false>(L, g, b, o);
+                    *reinterpret_cast<uint2 *>(ob + b) = make_uint2(o[0], o[1]);
+                }
+            }
+        } else if (OBSV == OBS_A16) {
             for (uint32_t k = lane; k < (B >> 4); k += kWave) {
                 const uint32_t b = k << 4;
                 const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
@@ -662,11 +703,18 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
                 }
                 *reinterpret_cast<uint4 *>(ob + b) = out;
             }
-        } else if (OBSV == OBS_A4 || OBSV == OBS_A1C16) {
+        } else if (OBSV == OBS_A4) {
             for (uint32_t k = lane; k < (B >> 4); k += kWave) {
                 const uint32_t b = k << 4;
                 uint32_t o[4];
-                obs_chunk<16, OBSV == OBS_A4>(L, g, b, o);
+                obs_chunk<16, true>(L, g, b, o);
+                *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        } else if (OBSV == OBS_A1C16) {
+            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
+                const uint32_t b = k << 4;
+                uint32_t o[4];
+                obs_chunk<16, false>(L, g, b, o);
                 *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
             }
         } else {
@@ -680,25 +728,112 @@ __global__ __launch_bounds__(64) void k_env(EnvArgs a)
     }
 
     // ---- fused random actor for the next step, on the final state
-    if (ACT) actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, a.actor_seed, a.step_idx, env_id,
-                        a.next_actions + (size_t)e * g.P);
+    if (ACT) actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, actor_seed, io.use_tick ? s.tick : io.actor_step,
+                        env_id, io.next_actions);
 
     // ---- rewards, done, scalars
     if (KIND == K_STEP) {
-        if (lane < g.P)
-            a.rewards[(size_t)e * g.P + lane] = ((win >> lane) & 1u) ? 1 : (((lose >> lane) & 1u) ? -1 : 0);
-        if (lane == 0) a.dones[e] = done ? 1 : 0;
+        if (lane < g.P) io.rewards[lane] = ((win >> lane) & 1u) ? 1 : (((lose >> lane) & 1u) ? -1 : 0);
+        if (lane == 0) *io.done = done ? 1 : 0;
     }
     if (KIND != K_OBSERVE && lane == 0) {
-        EnvScalars *d = a.sc + e;
+        EnvScalars *d = io.sc;
         d->turn = s.turn;
         d->episode = s.episode;
         d->alive = s.alive;
         d->finished = s.finished;
+        if (io.use_tick || KIND == K_RESET) d->tick = s.tick;
         if (write_type) {
 #pragma unroll
             for (int i = 0; i < kMaxP; ++i) d->gpos[i] = s.gpos[i];
         }
+    }
+}
+
+template <int KIND, int OBSV, bool SB, bool ACT>
+__global__ __launch_bounds__(64) void k_env(EnvArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int e = blockIdx.x;
+    const Geom g = a.g;
+    const size_t cell0 = (size_t)e * g.S;
+    EnvIO io;
+    io.sc = a.sc + e;
+    io.owner = a.owner + cell0;
+    io.type = a.type + cell0;
+    io.army = a.army + cell0;
+    io.actions = a.actions + (size_t)e * g.P;
+    io.next_actions = a.next_actions + (size_t)e * g.P;
+    io.rewards = a.rewards + (size_t)e * g.P;
+    io.done = a.dones + e;
+    io.obs = a.obs != nullptr ? a.obs + (size_t)e * (size_t)(g.P * 8 * g.HW) : nullptr;
+    io.land = a.land + (size_t)e * g.P;
+    io.army_tot = a.army_tot + (size_t)e * g.P;
+    io.env_id = a.env_base + (uint64_t)e;
+    io.actor_step = a.step_idx;
+    io.use_tick = false;
+    env_body<KIND, OBSV, SB, ACT>(smem, g, a.prm, a.seed, a.actor_seed, io);
+}
+
+// ---------------------------------------------------------------- batched pool (mixed shapes)
+// One wave per env, `wpg` envs per workgroup, envs taken in the order of a
+// work list; each env's shape, mode, generator settings and buffer offsets
+// come from its 32-byte descriptor.  With a grid smaller than the work list
+// the workgroups loop (persistent form).
+// One pool env on the calling wave (slot = position in the work list).
+template <int KIND, bool ACT>
+__device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint32_t slot)
+{
+    const uint32_t e = a.order[slot];
+    const PoolDesc d = a.desc[e];
+    Geom g;
+    g.H = d.H;
+    g.W = d.W;
+    g.HW = d.H * d.W;
+    g.S = (g.HW + 15) & ~15;
+    g.P = d.P;
+    g.mode = d.mode;
+    g.NW = (g.HW + 63) >> 6;
+    g.magic_w = d.magic_w;
+    g.magic_hw = d.magic_hw;
+    g.obsv = d.obsv;
+    GenParamsDev prm = a.prm;
+    prm.cmin = d.cmin;
+    prm.cmax = d.cmax;
+    prm.dmin = d.dmin;
+    EnvIO io;
+    io.sc = a.sc + e;
+    io.owner = a.owner + d.cell_off;
+    io.type = a.type + d.cell_off;
+    io.army = a.army + d.cell_off;
+    io.actions = a.actions + d.act_off;
+    io.next_actions = a.actions + d.act_off;
+    io.rewards = a.rewards + d.act_off;
+    io.done = a.dones + e;
+    io.obs = a.obs != nullptr ? a.obs + (size_t)d.obs_off16 * 16 : nullptr;
+    io.land = nullptr;
+    io.army_tot = nullptr;
+    io.env_id = a.env_base + e;
+    io.actor_step = 0;
+    io.use_tick = true;
+    env_body<KIND, OBS_RUNTIME, false, ACT>(smem, g, prm, a.seed, a.actor_seed, io);
+}
+
+// PERSIST = false: one env per wave, the grid covers the work list.
+// PERSIST = true: a smaller grid whose waves stride over the work list.
+template <int KIND, bool ACT, bool PERSIST>
+__global__ __launch_bounds__(256) void k_pool(PoolArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    // wave index as a scalar: everything derived from the env id stays wave-uniform
+    const uint32_t wave = (uint32_t)readfirst((int)(threadIdx.x >> 6));
+    uint8_t *mine = smem + wave * a.lds_per_wave;
+    if (PERSIST) {
+        for (uint32_t slot = blockIdx.x * a.wpg + wave; slot < a.n_envs; slot += gridDim.x * a.wpg)
+            pool_env<KIND, ACT>(a, mine, slot);
+    } else {
+        const uint32_t slot = blockIdx.x * a.wpg + wave;
+        if (slot < a.n_envs) pool_env<KIND, ACT>(a, mine, slot);
     }
 }
 
@@ -740,12 +875,14 @@ __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
 // ---------------------------------------------------------------- launchers
 uint32_t lds_bytes(const Geom &g) { return lds_bytes_for(g.S, g.P); }
 
-static int obs_variant(const Geom &g)
+int obs_variant(int HW, int P)
 {
-    if (g.HW % 16 == 0) return OBS_A16;
-    if (g.HW % 4 == 0) return OBS_A4;
-    return ((g.P * 8 * g.HW) % 16 == 0) ? OBS_A1C16 : OBS_A1C8;
+    if (HW % 16 == 0) return OBS_A16;
+    if (HW % 4 == 0) return OBS_A4;
+    return ((P * 8 * HW) % 16 == 0) ? OBS_A1C16 : OBS_A1C8;
 }
+
+static int obs_variant(const Geom &g) { return obs_variant(g.HW, g.P); }
 
 template <int KIND, bool SB, bool ACT>
 static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
@@ -778,6 +915,32 @@ hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream)
 hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
     return launch_kind<K_OBSERVE, false, false>(a, n_envs, stream);
+}
+
+template <int KIND, bool ACT, bool PERSIST>
+static hipError_t launch_pool_kind(const PoolArgs &a, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_pool<KIND, ACT, PERSIST>), dim3(grid), dim3(kWave * a.wpg), a.lds_per_wave * a.wpg,
+                       stream, a);
+    return hipGetLastError();
+}
+
+// grid == 0: one wave per env (ceil(n_envs / wpg) workgroups); else persistent.
+hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, hipStream_t stream)
+{
+    const uint32_t full = (a.n_envs + a.wpg - 1) / a.wpg;
+    if (grid == 0 || grid >= full) {
+        if (kind == K_RESET)
+            return act ? launch_pool_kind<K_RESET, true, false>(a, full, stream)
+                       : launch_pool_kind<K_RESET, false, false>(a, full, stream);
+        return act ? launch_pool_kind<K_STEP, true, false>(a, full, stream)
+                   : launch_pool_kind<K_STEP, false, false>(a, full, stream);
+    }
+    if (kind == K_RESET)
+        return act ? launch_pool_kind<K_RESET, true, true>(a, grid, stream)
+                   : launch_pool_kind<K_RESET, false, true>(a, grid, stream);
+    return act ? launch_pool_kind<K_STEP, true, true>(a, grid, stream)
+               : launch_pool_kind<K_STEP, false, true>(a, grid, stream);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int n_envs, hipStream_t stream)

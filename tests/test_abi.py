@@ -127,3 +127,37 @@ def test_one_hip_runtime_in_process():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split()[0] == "1", out.stdout
+
+
+def test_pool_plan_host_side(L):
+    import numpy as np
+    specs = {"H": np.array([10, 25, 3]), "W": np.array([12, 25, 3]), "mode": np.array([0, 1, 2]),
+             "P": np.array([2, 4, 3]), "cities_min": np.array([2, 8, 0]), "cities_max": np.array([3, 13, 1]),
+             "min_general_dist": np.array([9, 6, 1])}
+    h = gen.gen_pool_create(5, 0, specs)
+    info = gen.gen_pool_info()
+    assert L.gen_pool_query(h, ctypes.byref(info)) == 0
+    assert info.n_envs == 3 and info.max_cells == 625 and info.n_actions == 9
+    obs = np.zeros(3, np.uint64)
+    act = np.zeros(3, np.uint32)
+    assert L.gen_pool_offsets(h, obs.ctypes.data, act.ctypes.data) == 0
+    sizes = [2 * 8 * 120, 4 * 8 * 625, 3 * 8 * 9]
+    assert obs.tolist() == [0, (sizes[0] + 15) // 16 * 16, ((sizes[0] + 15) // 16 + (sizes[1] + 15) // 16) * 16]
+    assert act.tolist() == [0, 2, 6]
+    assert info.obs_bytes == sum((s + 15) // 16 * 16 for s in sizes)
+    bad = gen.gen_pool_tuning(3, 0, 0, 0)
+    assert L.gen_pool_set_tuning(h, ctypes.byref(bad), None) == gen.GEN_EINVAL
+    ok = gen.gen_pool_tuning(4, 64, 1, 0)
+    assert L.gen_pool_set_tuning(h, ctypes.byref(ok), None) == 0        # not bound: nothing uploaded
+    assert L.gen_pool_step(h, None, 1, 0, None, None, None, None) == gen.GEN_EINVAL
+    assert "gen_pool_reset" in gen.gen_last_error()
+    L.gen_pool_destroy(h)
+
+
+def test_pool_rejects_bad_spec(L):
+    import numpy as np
+    specs = {"H": np.array([10, 40]), "W": np.array([10, 10]), "mode": np.array([0, 0]), "P": np.array([2, 2]),
+             "cities_min": np.array([1, 1]), "cities_max": np.array([2, 2]), "min_general_dist": np.array([3, 3])}
+    with pytest.raises(gen.GenError) as ei:
+        gen.gen_pool_create(1, 0, specs)
+    assert "env spec 1" in str(ei.value)
