@@ -262,6 +262,77 @@ int gen_pool_replay(gen_pool *pool, void *stream);
 /* Blocking copy of one env in the public host format (one row of H*W cells). */
 int gen_pool_get_env(const gen_pool *pool, int32_t env, gen_host_state *h, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Served form: an environment server with continuous batching.
+ * The caller hands the server one device arena; its size is the memory
+ * budget.  Each opened group (a pool of envs of any shapes and modes) gets
+ * its state, observations, actions, rewards and done flags carved out of the
+ * arena, or GEN_EBUDGET when they do not fit.  Step requests from any number
+ * of client threads are queued; a scheduler thread gathers the requests of
+ * every group that is not already on the GPU into one launch (envs of
+ * different groups and sizes side by side), keeps up to n_launch_streams
+ * launches in flight, and completes tickets when their launch finishes.
+ * A group is never in two launches at once, and every env is independent,
+ * so results do not depend on how requests were batched.
+ * ---------------------------------------------------------------------- */
+typedef struct gen_server gen_server;
+
+typedef struct gen_group_buffers {
+    uint64_t state_off;         /* byte offsets into the arena */
+    uint64_t obs_off;           /* ragged observations, per-env offsets from gen_pool_offsets(pool) */
+    uint64_t actions_off, rewards_off, dones_off;
+    uint64_t obs_bytes, n_actions;
+    int32_t n_envs, reserved;
+    gen_pool *pool;             /* the group's plan (offsets, gen_pool_get_env); owned by the server */
+} gen_group_buffers;
+
+typedef struct gen_server_stats {
+    uint64_t requests, frames, launches, groups_open, groups_refused;
+    uint64_t arena_bytes, bytes_in_use;
+    double lat_p50_us, lat_p99_us, lat_mean_us;   /* submit -> completion seen by the server */
+    double envs_per_launch;
+    double wall_s;              /* gen_server_drive: length of the measured window */
+} gen_server_stats;
+
+/* d_arena: device buffer of arena_bytes (256-byte aligned) the server may
+ * use; n_launch_streams: launches in flight (1..4); max_batch_envs: cap on
+ * envs per launch (0 = no cap).  Starts the scheduler thread. */
+int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_streams, int32_t max_batch_envs,
+                      gen_server **out);
+/* Finishes the work in flight, stops the scheduler, releases host objects. */
+int gen_server_destroy(gen_server *srv);
+/* Admit a group: plan, carve its buffers, generate its maps (blocking).
+ * actor != 0: every step also draws the group's next actions with the random
+ * actor (seed actor_seed, each env's own step counter); else the caller
+ * writes actions into the group's action buffer before each request. */
+int gen_server_open(gen_server *srv, uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
+                    const gen_params *common, int32_t actor, uint64_t actor_seed, uint64_t *group);
+int gen_server_buffers(gen_server *srv, uint64_t group, gen_group_buffers *out);
+/* Queue one step of every env of the group; *ticket identifies it. */
+int gen_server_submit(gen_server *srv, uint64_t group, uint64_t *ticket);
+/* GEN_OK when the step is done (its outputs are in the group's buffers),
+ * GEN_EBUSY if timeout_us passed first (timeout_us < 0: wait forever),
+ * GEN_ENOTFOUND for an unknown or already collected ticket. */
+int gen_server_wait(gen_server *srv, uint64_t ticket, int64_t timeout_us);
+/* Waits for the group's work in flight, drops its queued requests (their
+ * tickets fail with GEN_ENOTFOUND) and returns its memory to the arena. */
+int gen_server_close(gen_server *srv, uint64_t group);
+int gen_server_report(gen_server *srv, gen_server_stats *out, int32_t reset);
+
+/* Synthetic clients for measuring the server (load generator, not part of
+ * the step): n_clients threads, each owning groups_per_client groups opened
+ * from h_specs (env specs of all groups back to back, group g has
+ * h_group_envs[g] envs), issuing closed-loop requests -- a group's next
+ * request only after its previous one completed -- paced by the arrival gaps
+ * h_gaps_us[client][k] (microseconds; all zero = back to back), until
+ * duration_us has passed.  A group that reached steps_per_group steps is
+ * closed and reopened (same specs, next env ids) when steps_per_group > 0.
+ * Returns the stats of the run. */
+int gen_server_drive(gen_server *srv, int32_t n_clients, int32_t groups_per_client, const int32_t *h_group_envs,
+                     const gen_env_spec *h_specs, const gen_params *common, uint64_t seed, uint64_t actor_seed,
+                     const double *h_gaps_us, int32_t gaps_per_client, int64_t duration_us, int32_t steps_per_group,
+                     gen_server_stats *out);
+
 /* Blocking copy of selected envs only: env h_env_ids[i] (0 <= id < n_envs)
  * goes to row i of each host array, which therefore hold n_ids rows.  For
  * checkpoints of part of a batch and for sampled parity checks. */

@@ -65,6 +65,21 @@ class gen_pool_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("waves_per_group", "grid", "order", "reserved")]
 
 
+class gen_group_buffers(ctypes.Structure):
+    _fields_ = [("state_off", ctypes.c_uint64), ("obs_off", ctypes.c_uint64), ("actions_off", ctypes.c_uint64),
+                ("rewards_off", ctypes.c_uint64), ("dones_off", ctypes.c_uint64), ("obs_bytes", ctypes.c_uint64),
+                ("n_actions", ctypes.c_uint64), ("n_envs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pool", ctypes.c_void_p)]
+
+
+class gen_server_stats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("frames", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("groups_open", ctypes.c_uint64), ("groups_refused", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("lat_p50_us", ctypes.c_double), ("lat_p99_us", ctypes.c_double), ("lat_mean_us", ctypes.c_double),
+                ("envs_per_launch", ctypes.c_double), ("wall_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -109,11 +124,23 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_pool_capture.argtypes = [vp, i32, vp, u64, vp, vp, vp, vp]
     L.gen_pool_replay.argtypes = [vp, vp]
     L.gen_pool_get_env.argtypes = [vp, i32, P(gen_host_state), vp]
+    L.gen_server_create.argtypes = [vp, u64, i32, i32, P(vp)]
+    L.gen_server_destroy.argtypes = [vp]
+    L.gen_server_open.argtypes = [vp, u64, u64, i32, vp, P(gen_params), i32, u64, P(ctypes.c_uint64)]
+    L.gen_server_buffers.argtypes = [vp, u64, P(gen_group_buffers)]
+    L.gen_server_submit.argtypes = [vp, u64, P(ctypes.c_uint64)]
+    L.gen_server_wait.argtypes = [vp, u64, ctypes.c_int64]
+    L.gen_server_close.argtypes = [vp, u64]
+    L.gen_server_report.argtypes = [vp, P(gen_server_stats), i32]
+    L.gen_server_drive.argtypes = [vp, i32, i32, vp, vp, P(gen_params), u64, u64, vp, i32, ctypes.c_int64, i32,
+                                   P(gen_server_stats)]
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
               "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
-              "gen_pool_get_env"):
+              "gen_pool_get_env", "gen_server_create", "gen_server_destroy", "gen_server_open",
+              "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
+              "gen_server_report", "gen_server_drive"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -376,3 +403,104 @@ class Pool:
     def env_slice(self, e: int):
         a = int(self.act_off[e])
         return slice(a, a + int(self.specs["P"][e]))
+
+
+# ---------------------------------------------------------------------------- served form
+def _spec_array(specs: dict, lo: int = 0, hi: int | None = None):
+    hi = len(specs["H"]) if hi is None else hi
+    arr = (gen_env_spec * (hi - lo))()
+    for i in range(lo, hi):
+        arr[i - lo] = gen_env_spec(int(specs["H"][i]), int(specs["W"][i]), int(specs["mode"][i]),
+                                   int(specs["P"][i]), int(specs["cities_min"][i]), int(specs["cities_max"][i]),
+                                   int(specs["min_general_dist"][i]), 0)
+    return arr
+
+
+def _stats_dict(st: gen_server_stats) -> dict:
+    return {k: getattr(st, k) for k, _ in gen_server_stats._fields_}
+
+
+class Server:
+    """An environment server over a torch-allocated device arena (the
+    memory budget).  Every method is one library call."""
+
+    def __init__(self, arena_bytes: int, n_launch_streams: int = 2, max_batch_envs: int = 0,
+                 device: str = "cuda"):
+        import torch
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(lib().gen_server_create(_ptr(self.arena), arena_bytes, n_launch_streams, max_batch_envs,
+                                       ctypes.byref(self.handle)))
+
+    def close_server(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gen_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close_server()
+
+    def open(self, specs: dict, seed: int, env_base: int = 0, common: gen_params | None = None,
+             actor_seed: int | None = None) -> int:
+        arr = _spec_array(specs)
+        gid = ctypes.c_uint64()
+        _check(lib().gen_server_open(self.handle, seed, env_base, len(arr), arr,
+                                     ctypes.byref(common) if common else None, 1 if actor_seed is not None else 0,
+                                     actor_seed or 0, ctypes.byref(gid)))
+        return gid.value
+
+    def buffers(self, group: int) -> dict:
+        b = gen_group_buffers()
+        _check(lib().gen_server_buffers(self.handle, group, ctypes.byref(b)))
+        n = b.n_envs
+        obs_off = np.zeros(n, np.uint64)
+        act_off = np.zeros(n, np.uint32)
+        _check(lib().gen_pool_offsets(b.pool, obs_off.ctypes.data, act_off.ctypes.data))
+        a = self.arena
+        return {"n_envs": n, "pool": b.pool, "obs_off": obs_off, "act_off": act_off,
+                "obs": a[b.obs_off:b.obs_off + b.obs_bytes],
+                "actions": a[b.actions_off:b.actions_off + 4 * b.n_actions].view(__import__("torch").int32),
+                "rewards": a[b.rewards_off:b.rewards_off + 4 * b.n_actions].view(__import__("torch").int32),
+                "dones": a[b.dones_off:b.dones_off + n]}
+
+    def get_env(self, group: int, e: int, H: int, W: int, P: int) -> dict:
+        b = gen_group_buffers()
+        _check(lib().gen_server_buffers(self.handle, group, ctypes.byref(b)))
+        h = _host_arrays(1, H * W, P)
+        hs = _host_struct(h)
+        _check(lib().gen_pool_get_env(b.pool, e, ctypes.byref(hs), None))
+        return h
+
+    def submit(self, group: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().gen_server_submit(self.handle, group, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        rc = lib().gen_server_wait(self.handle, ticket, timeout_us)
+        if rc not in (GEN_OK, GEN_EBUSY):
+            _check(rc)
+        return rc
+
+    def close(self, group: int):
+        _check(lib().gen_server_close(self.handle, group))
+
+    def report(self, reset: bool = False) -> dict:
+        st = gen_server_stats()
+        _check(lib().gen_server_report(self.handle, ctypes.byref(st), 1 if reset else 0))
+        return _stats_dict(st)
+
+    def drive(self, group_envs, specs: dict, seed: int, actor_seed: int, gaps_us, duration_s: float,
+              steps_per_group: int = 0, common: gen_params | None = None) -> dict:
+        """Native closed-loop clients (see gen_server_drive).  gaps_us: array
+        [n_clients, k] of inter-arrival gaps in microseconds."""
+        gaps = np.ascontiguousarray(np.asarray(gaps_us, np.float64))
+        n_clients, k = gaps.shape
+        ge = np.ascontiguousarray(np.asarray(group_envs, np.int32))
+        groups_per_client = len(ge) // n_clients
+        arr = _spec_array(specs)
+        st = gen_server_stats()
+        _check(lib().gen_server_drive(self.handle, n_clients, groups_per_client, ge.ctypes.data, arr,
+                                      ctypes.byref(common) if common else None, seed, actor_seed, gaps.ctypes.data,
+                                      k, int(duration_s * 1e6), steps_per_group, ctypes.byref(st)))
+        return _stats_dict(st)

@@ -82,19 +82,6 @@ gen::Geom geom_of(const gen_state &st)
     return g;
 }
 
-gen::GenParamsDev prm_of(const gen_params &p)
-{
-    gen::GenParamsDev d;
-    d.thresh = p.mountain_thresh;
-    d.cmin = p.cities_min;
-    d.cmax = p.cities_max;
-    d.amin = p.city_army_min;
-    d.amax = p.city_army_max;
-    d.dmin = p.min_general_dist;
-    d.auto_reset = p.auto_reset;
-    d.pregrow = p.pregrow;
-    return d;
-}
 
 int check_state(const gen_state *st)
 {
@@ -114,7 +101,7 @@ gen::EnvArgs env_args(const gen_state &st)
 {
     gen::EnvArgs a{};
     a.g = geom_of(st);
-    a.prm = prm_of(st.params);
+    a.prm = gen::prm_of(st.params);
     a.seed = st.seed;
     a.env_base = st.env_base;
     uint8_t *base = static_cast<uint8_t *>(st.d_buf);
@@ -138,24 +125,6 @@ int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
 
 }  // namespace
 
-// Host plan of a batched pool (see generals.h).
-struct gen_pool {
-    uint64_t seed = 0, env_base = 0;
-    int32_t n = 0;
-    gen_params common{};
-    std::vector<gen::PoolDesc> desc;
-    std::vector<uint64_t> work;           // P*H*W per env, for the work order
-    std::vector<uint32_t> order;
-    uint64_t off_scalars = 0, off_desc = 0, off_order = 0, off_owner = 0, off_type = 0, off_army = 0;
-    uint64_t state_bytes = 0, obs_bytes = 0, n_actions = 0;
-    uint32_t lds_per_wave = 0;
-    int32_t max_cells = 0;
-    gen_pool_tuning tuning{1, 0, 0, 0};
-    void *d_state = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
 namespace {
 
 void pool_make_order(gen_pool &pl)
@@ -171,7 +140,7 @@ void pool_make_order(gen_pool &pl)
 gen::PoolArgs pool_args(const gen_pool &pl)
 {
     gen::PoolArgs a{};
-    a.prm = prm_of(pl.common);
+    a.prm = gen::prm_of(pl.common);
     a.seed = pl.seed;
     a.env_base = pl.env_base;
     a.n_envs = (uint32_t)pl.n;
@@ -203,6 +172,12 @@ int check_bound(const gen_pool *pl)
 }
 
 }  // namespace
+
+int gen::set_error(int code, const char *msg)
+{
+    g_last_error = msg ? msg : "";
+    return code;
+}
 
 extern "C" {
 
@@ -598,6 +573,7 @@ int gen_pool_reset(gen_pool *pool, void *d_state, uint64_t state_bytes, uint8_t 
     a.obs = d_obs;
     a.actions = d_actions;
     a.actor_seed = actor_seed;
+    a.actor = d_actions != nullptr ? 1u : 0u;
     e = gen::launch_pool(a, 1 /* reset */, d_actions != nullptr, (uint32_t)pool->tuning.grid, s);
     if (e != hipSuccess) return hip_fail(e, "pool reset launch");
     return ok();
@@ -617,6 +593,7 @@ int gen_pool_step(gen_pool *pool, int32_t *d_actions, int32_t actor, uint64_t ac
     a.rewards = d_rewards;
     a.dones = d_dones;
     a.actor_seed = actor_seed;
+    a.actor = actor != 0 ? 1u : 0u;
     hipError_t e = gen::launch_pool(a, 0 /* step */, actor != 0, (uint32_t)pool->tuning.grid,
                                     static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "pool step launch");
@@ -640,6 +617,7 @@ int gen_pool_capture(gen_pool *pool, int32_t k_steps, int32_t *d_actions, uint64
     a.rewards = d_rewards;
     a.dones = d_dones;
     a.actor_seed = actor_seed;
+    a.actor = 1u;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
     for (int32_t k = 0; k < k_steps && e == hipSuccess; ++k) e = gen::launch_pool(a, 0, true, (uint32_t)pool->tuning.grid, s);

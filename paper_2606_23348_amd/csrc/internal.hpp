@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "../../include/generals.h"
 #include "device.hpp"
 
 namespace gen {
@@ -40,6 +43,7 @@ struct PoolArgs {
     GenParamsDev prm;            // common settings; cities and spawn distance per env
     uint64_t seed, env_base, actor_seed;
     uint32_t n_envs, wpg, lds_per_wave;
+    uint32_t actor;              // 1: draw the next actions after the step (ACT kernels)
     const PoolDesc *desc;
     const uint32_t *order;       // work list: env of each slot
     EnvScalars *sc;
@@ -52,8 +56,21 @@ struct PoolArgs {
     uint8_t *obs;
 };
 
+// One request of a served batch: one step of a group whose buffers all live
+// in the server's arena (byte offsets from the arena base), and the first
+// workgroup of its envs in the launch.
+struct ServeReq {
+    uint64_t off_desc, off_order, off_sc, off_owner, off_type, off_army;
+    uint64_t off_actions, off_rewards, off_dones, off_obs;
+    uint64_t seed, env_base, actor_seed;
+    GenParamsDev prm;
+    uint32_t n_envs, actor, wg_begin, pad;
+};
+
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);
+hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,
+                        hipStream_t stream);
 int obs_variant(int HW, int P);
 hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, hipStream_t stream);
 hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream);
@@ -61,4 +78,39 @@ hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream);
 hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream);
 hipError_t launch_sample(const SampleArgs &a, int n_envs, hipStream_t stream);
 
+// Sets the calling thread's gen_last_error() message; returns code.
+int set_error(int code, const char *msg);
+
+inline GenParamsDev prm_of(const gen_params &p)
+{
+    GenParamsDev d;
+    d.thresh = p.mountain_thresh;
+    d.cmin = p.cities_min;
+    d.cmax = p.cities_max;
+    d.amin = p.city_army_min;
+    d.amax = p.city_army_max;
+    d.dmin = p.min_general_dist;
+    d.auto_reset = p.auto_reset;
+    d.pregrow = p.pregrow;
+    return d;
+}
+
 }  // namespace gen
+
+// Host plan of a batched pool (see generals.h).
+struct gen_pool {
+    uint64_t seed = 0, env_base = 0;
+    int32_t n = 0;
+    gen_params common{};
+    std::vector<gen::PoolDesc> desc;
+    std::vector<uint64_t> work;           // P*H*W per env, for the work order
+    std::vector<uint32_t> order;
+    uint64_t off_scalars = 0, off_desc = 0, off_order = 0, off_owner = 0, off_type = 0, off_army = 0;
+    uint64_t state_bytes = 0, obs_bytes = 0, n_actions = 0;
+    uint32_t lds_per_wave = 0;
+    int32_t max_cells = 0;
+    gen_pool_tuning tuning{1, 0, 0, 0};
+    void *d_state = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};

@@ -728,8 +728,9 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     }
 
     // ---- fused random actor for the next step, on the final state
-    if (ACT) actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, actor_seed, io.use_tick ? s.tick : io.actor_step,
-                        env_id, io.next_actions);
+    if (ACT && io.next_actions != nullptr)
+        actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, actor_seed, io.use_tick ? s.tick : io.actor_step, env_id,
+                   io.next_actions);
 
     // ---- rewards, done, scalars
     if (KIND == K_STEP) {
@@ -807,7 +808,7 @@ __device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint3
     io.type = a.type + d.cell_off;
     io.army = a.army + d.cell_off;
     io.actions = a.actions + d.act_off;
-    io.next_actions = a.actions + d.act_off;
+    io.next_actions = a.actor ? a.actions + d.act_off : nullptr;
     io.rewards = a.rewards + d.act_off;
     io.done = a.dones + e;
     io.obs = a.obs != nullptr ? a.obs + (size_t)d.obs_off16 * 16 : nullptr;
@@ -915,6 +916,53 @@ hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream)
 hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
     return launch_kind<K_OBSERVE, false, false>(a, n_envs, stream);
+}
+
+// ---------------------------------------------------------------- served batches
+// One launch steps the envs of many requests (each request = one step of a
+// group, a pool of its own).  Workgroup w belongs to the request r with
+// reqs[r].wg_begin <= w < reqs[r + 1].wg_begin, found by a binary search over
+// the request table (wave-uniform loads).
+// Buffers are addressed as arena + offset so that every pointer derives from
+// a kernel argument (global address space, scalar base + vector offset).
+__global__ __launch_bounds__(64) void k_serve(uint8_t *arena, const ServeReq *__restrict__ reqs, uint32_t n_req)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t w = blockIdx.x;
+    uint32_t lo = 0, hi = n_req;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (reqs[mid].wg_begin <= w) lo = mid; else hi = mid;
+    }
+    const ServeReq &r = reqs[readfirst((int)lo)];
+    PoolArgs a;
+    a.prm = r.prm;
+    a.seed = r.seed;
+    a.env_base = r.env_base;
+    a.actor_seed = r.actor_seed;
+    a.n_envs = r.n_envs;
+    a.wpg = 1;
+    a.lds_per_wave = 0;
+    a.actor = r.actor;
+    a.desc = reinterpret_cast<const PoolDesc *>(arena + r.off_desc);
+    a.order = reinterpret_cast<const uint32_t *>(arena + r.off_order);
+    a.sc = reinterpret_cast<EnvScalars *>(arena + r.off_sc);
+    a.owner = reinterpret_cast<int8_t *>(arena + r.off_owner);
+    a.type = arena + r.off_type;
+    a.army = reinterpret_cast<int32_t *>(arena + r.off_army);
+    a.actions = reinterpret_cast<int32_t *>(arena + r.off_actions);
+    a.rewards = reinterpret_cast<int32_t *>(arena + r.off_rewards);
+    a.dones = arena + r.off_dones;
+    a.obs = r.off_obs != ~0ull ? arena + r.off_obs : nullptr;
+    const uint32_t slot = w - r.wg_begin;
+    if (slot < a.n_envs) pool_env<K_STEP, true>(a, smem, slot);
+}
+
+hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_serve, dim3(n_wg), dim3(kWave), lds, stream, arena, d_reqs, n_req);
+    return hipGetLastError();
 }
 
 template <int KIND, bool ACT, bool PERSIST>

@@ -1,0 +1,587 @@
+// server.cpp -- the served form of the batched Generals.io step: an
+// environment server with continuous batching over a caller-provided device
+// arena (see generals.h).
+//
+// Threads: client threads call open / submit / wait / close; one scheduler
+// thread owns every launch.  It drains the request queue, puts the requests
+// of all groups that are not on the GPU into one launch of k_serve (a table
+// of requests, one workgroup per env), keeps up to n_launch_streams launches
+// in flight on their own streams, polls their completion events and wakes
+// the waiting clients.  Requests that arrive while launches run form the
+// next launch as soon as a stream frees up.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/generals.h"
+#include "internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+int64_t now_ns() { return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count(); }
+
+// First-fit allocator over [0, size) of the arena, 256-byte granules.
+class Arena {
+  public:
+    void init(uint64_t size) { free_.clear(); free_[0] = size; size_ = size; used_ = 0; }
+    bool alloc(uint64_t n, uint64_t *off)
+    {
+        n = (n + 255) & ~uint64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        n = (n + 255) & ~uint64_t(255);
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) { it->second += nx->second; free_.erase(nx); }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) { pv->second += it->second; free_.erase(it); }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return size_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0, used_ = 0;
+};
+
+struct Group {
+    uint64_t id = 0;
+    gen_pool *pool = nullptr;
+    int32_t n_envs = 0;
+    int32_t actor = 0;
+    uint64_t actor_seed = 0;
+    uint64_t off_state = 0, off_obs = 0, off_act = 0, off_rew = 0, off_done = 0;
+    uint64_t sz_state = 0, sz_obs = 0, sz_act = 0, sz_done = 0;
+    bool busy = false;          // a request of this group is in a launch
+    bool closing = false;
+    int waiters = 0;            // clients blocked on cv (close waits for them to leave)
+    std::condition_variable cv; // completion of this group's tickets
+};
+
+struct Ticket {
+    uint64_t group;
+    int64_t t_submit;
+    int status;                 // 1 pending, 0 done, <0 failed
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<std::pair<uint64_t, uint64_t>> reqs;   // (ticket, group)
+    gen::ServeReq *h_table = nullptr;                  // pinned
+    uint64_t d_table_off = 0;                          // in the arena
+    uint64_t envs = 0;
+};
+
+}  // namespace
+
+struct gen_server {
+    uint8_t *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    int device = 0;
+    uint32_t max_batch_envs = 0;
+    uint32_t max_reqs = 0;
+    Arena alloc;
+    std::mutex mu;
+    std::condition_variable cv_sched;
+    std::unordered_map<uint64_t, std::unique_ptr<Group>> groups;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    std::deque<uint64_t> queue;                        // pending tickets, arrival order
+    std::vector<Slot> slots;
+    uint64_t next_group = 1, next_ticket = 1;
+    std::thread sched;
+    bool stop = false;
+    std::string error;                                 // sticky scheduler error
+    // stats
+    uint64_t st_requests = 0, st_frames = 0, st_launches = 0, st_refused = 0, st_launch_envs = 0;
+    std::vector<float> lat_us;
+};
+
+namespace {
+
+int sfail(int code, const std::string &msg) { return gen::set_error(code, msg.c_str()); }
+
+void complete_slot(gen_server &s, Slot &sl, int status)
+{
+    const int64_t t = now_ns();
+    for (auto &[tk, gid] : sl.reqs) {
+        auto it = s.tickets.find(tk);
+        if (it != s.tickets.end()) {
+            it->second.status = status;
+            if (status == 0) s.lat_us.push_back((float)((t - it->second.t_submit) / 1000.0));
+        }
+        auto g = s.groups.find(gid);
+        if (g != s.groups.end()) {
+            g->second->busy = false;
+            if (status == 0) {
+                s.st_requests += 1;
+                s.st_frames += (uint64_t)g->second->n_envs;
+            }
+            g->second->cv.notify_all();
+        }
+    }
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
+void fill_req(const gen_server &s, const Group &g, uint32_t wg_begin, gen::ServeReq *r)
+{
+    const gen_pool &pl = *g.pool;
+    std::memset(r, 0, sizeof *r);
+    r->off_desc = g.off_state + pl.off_desc;
+    r->off_order = g.off_state + pl.off_order;
+    r->off_sc = g.off_state + pl.off_scalars;
+    r->off_owner = g.off_state + pl.off_owner;
+    r->off_type = g.off_state + pl.off_type;
+    r->off_army = g.off_state + pl.off_army;
+    r->off_actions = g.off_act;
+    r->off_rewards = g.off_rew;
+    r->off_dones = g.off_done;
+    r->off_obs = g.off_obs;
+    r->seed = pl.seed;
+    r->env_base = pl.env_base;
+    r->actor_seed = g.actor_seed;
+    r->prm = gen::prm_of(pl.common);
+    r->n_envs = (uint32_t)pl.n;
+    r->actor = g.actor ? 1u : 0u;
+    r->wg_begin = wg_begin;
+    (void)s;
+}
+
+void scheduler(gen_server *sp)
+{
+    gen_server &s = *sp;
+    (void)hipSetDevice(s.device);
+    std::unique_lock<std::mutex> lk(s.mu);
+    while (true) {
+        bool progressed = false;
+        // completions
+        for (auto &sl : s.slots) {
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipSuccess) {
+                complete_slot(s, sl, 0);
+                progressed = true;
+            } else if (q != hipErrorNotReady) {
+                s.error = std::string("launch failed: ") + hipGetErrorString(q);
+                complete_slot(s, sl, GEN_EHIP);
+                progressed = true;
+            }
+        }
+        if (s.stop && s.queue.empty() && std::none_of(s.slots.begin(), s.slots.end(), [](const Slot &x) { return x.busy; }))
+            break;
+        // form a launch from the queue: every request whose group is free
+        Slot *free_slot = nullptr;
+        for (auto &sl : s.slots)
+            if (!sl.busy) { free_slot = &sl; break; }
+        if (free_slot && !s.queue.empty() && s.error.empty()) {
+            Slot &sl = *free_slot;
+            uint32_t n_req = 0, wg = 0, lds = 0;
+            for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
+                auto tk = s.tickets.find(*it);
+                if (tk == s.tickets.end() || tk->second.status != 1) { it = s.queue.erase(it); continue; }
+                auto gi = s.groups.find(tk->second.group);
+                if (gi == s.groups.end() || gi->second->closing) {
+                    tk->second.status = GEN_ENOTFOUND;
+                    it = s.queue.erase(it);
+                    continue;
+                }
+                Group &g = *gi->second;
+                if (g.busy || (s.max_batch_envs && n_req > 0 && wg + (uint32_t)g.n_envs > s.max_batch_envs)) { ++it; continue; }
+                g.busy = true;
+                fill_req(s, g, wg, &sl.h_table[n_req]);
+                sl.reqs.emplace_back(*it, g.id);
+                wg += (uint32_t)g.n_envs;
+                lds = std::max(lds, g.pool->lds_per_wave);
+                ++n_req;
+                it = s.queue.erase(it);
+            }
+            if (n_req > 0) {
+                sl.busy = true;
+                sl.envs = wg;
+                s.st_launches += 1;
+                s.st_launch_envs += wg;
+                gen::ServeReq *d_table = reinterpret_cast<gen::ServeReq *>(s.arena + sl.d_table_off);
+                lk.unlock();
+                hipError_t e = hipMemcpyAsync(d_table, sl.h_table, n_req * sizeof(gen::ServeReq),
+                                              hipMemcpyHostToDevice, sl.stream);
+                if (e == hipSuccess) e = gen::launch_serve(s.arena, d_table, n_req, wg, lds, sl.stream);
+                if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+                lk.lock();
+                if (e != hipSuccess) {
+                    s.error = std::string("launch failed: ") + hipGetErrorString(e);
+                    complete_slot(s, sl, GEN_EHIP);
+                }
+                progressed = true;
+            }
+        }
+        if (!progressed) {
+            const bool inflight = std::any_of(s.slots.begin(), s.slots.end(), [](const Slot &x) { return x.busy; });
+            if (inflight) s.cv_sched.wait_for(lk, std::chrono::microseconds(10));
+            else s.cv_sched.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_streams, int32_t max_batch_envs,
+                      gen_server **out)
+{
+    if (out == nullptr) return sfail(GEN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d_arena == nullptr || (reinterpret_cast<uintptr_t>(d_arena) & 255)) return sfail(GEN_EINVAL, "arena must be 256-byte aligned");
+    if (n_launch_streams < 1 || n_launch_streams > 4) return sfail(GEN_EINVAL, "n_launch_streams must be 1..4");
+    if (max_batch_envs < 0) return sfail(GEN_EINVAL, "max_batch_envs must be >= 0");
+    auto s = std::make_unique<gen_server>();
+    s->arena = static_cast<uint8_t *>(d_arena);
+    s->arena_bytes = arena_bytes;
+    s->max_batch_envs = (uint32_t)max_batch_envs;
+    s->max_reqs = 8192;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_arena) != hipSuccess) return sfail(GEN_EINVAL, "arena is not device memory");
+    s->device = attr.device;
+    (void)hipSetDevice(s->device);
+    s->alloc.init(arena_bytes);
+    const uint64_t table_bytes = (uint64_t)s->max_reqs * sizeof(gen::ServeReq);
+    s->slots.resize((size_t)n_launch_streams);
+    for (auto &sl : s->slots) {
+        if (!s->alloc.alloc(table_bytes, &sl.d_table_off)) return sfail(GEN_EBUDGET, "arena too small for the request tables");
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.h_table), table_bytes, hipHostMallocDefault) != hipSuccess)
+            return sfail(GEN_EHIP, "stream, event or pinned table allocation failed");
+    }
+    s->sched = std::thread(scheduler, s.get());
+    *out = s.release();
+    return GEN_OK;
+}
+
+int gen_server_destroy(gen_server *s)
+{
+    if (s == nullptr) return GEN_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_sched.notify_all();
+    if (s->sched.joinable()) s->sched.join();
+    for (auto &sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.h_table) (void)hipHostFree(sl.h_table);
+    }
+    for (auto &[id, g] : s->groups) gen_pool_destroy(g->pool);
+    delete s;
+    return GEN_OK;
+}
+
+int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
+                    const gen_params *common, int32_t actor, uint64_t actor_seed, uint64_t *group)
+{
+    if (s == nullptr || group == nullptr) return sfail(GEN_EINVAL, "server and group are required");
+    gen_pool *pool = nullptr;
+    int rc = gen_pool_create(seed, env_base, n_envs, h_specs, common, &pool);
+    if (rc != GEN_OK) return sfail(rc, gen_last_error());
+    auto g = std::make_unique<Group>();
+    g->pool = pool;
+    g->n_envs = n_envs;
+    g->actor = actor;
+    g->actor_seed = actor_seed;
+    g->sz_state = pool->state_bytes;
+    g->sz_obs = std::max<uint64_t>(pool->obs_bytes, 16);
+    g->sz_act = pool->n_actions * 4;
+    g->sz_done = (uint64_t)n_envs;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        uint64_t o[5];
+        const uint64_t sz[5] = {g->sz_state, g->sz_obs, g->sz_act, g->sz_act, g->sz_done};
+        int k = 0;
+        for (; k < 5; ++k)
+            if (!s->alloc.alloc(sz[k], &o[k])) break;
+        if (k < 5) {
+            for (int j = 0; j < k; ++j) s->alloc.release(o[j], sz[j]);
+            s->st_refused += 1;
+            gen_pool_destroy(pool);
+            return sfail(GEN_EBUDGET, "group of " + std::to_string(n_envs) + " envs does not fit in the arena");
+        }
+        g->off_state = o[0];
+        g->off_obs = o[1];
+        g->off_act = o[2];
+        g->off_rew = o[3];
+        g->off_done = o[4];
+        g->id = s->next_group++;
+        g->busy = true;          // until its maps exist
+    }
+    // generate the maps on this thread's own stream, blocking
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        rc = gen_pool_reset(pool, s->arena + g->off_state, g->sz_state, s->arena + g->off_obs,
+                            actor ? reinterpret_cast<int32_t *>(s->arena + g->off_act) : nullptr, actor_seed, st);
+        if (rc == GEN_OK) e = hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (e != hipSuccess || rc != GEN_OK) {
+        const uint64_t sz[5] = {g->sz_state, g->sz_obs, g->sz_act, g->sz_act, g->sz_done};
+        const uint64_t o[5] = {g->off_state, g->off_obs, g->off_act, g->off_rew, g->off_done};
+        for (int j = 0; j < 5; ++j) s->alloc.release(o[j], sz[j]);
+        gen_pool_destroy(pool);
+        return sfail(e != hipSuccess ? GEN_EHIP : rc, e != hipSuccess ? hipGetErrorString(e) : gen_last_error());
+    }
+    g->busy = false;
+    *group = g->id;
+    s->groups[g->id] = std::move(g);
+    return GEN_OK;
+}
+
+int gen_server_buffers(gen_server *s, uint64_t group, gen_group_buffers *out)
+{
+    if (s == nullptr || out == nullptr) return sfail(GEN_EINVAL, "server and out are required");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->groups.find(group);
+    if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
+    const Group &g = *it->second;
+    out->state_off = g.off_state;
+    out->obs_off = g.off_obs;
+    out->actions_off = g.off_act;
+    out->rewards_off = g.off_rew;
+    out->dones_off = g.off_done;
+    out->obs_bytes = g.pool->obs_bytes;
+    out->n_actions = g.pool->n_actions;
+    out->n_envs = g.n_envs;
+    out->reserved = 0;
+    out->pool = g.pool;
+    return GEN_OK;
+}
+
+int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
+{
+    if (s == nullptr || ticket == nullptr) return sfail(GEN_EINVAL, "server and ticket are required");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->error.empty()) return sfail(GEN_EHIP, s->error);
+        auto it = s->groups.find(group);
+        if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
+        const uint64_t tk = s->next_ticket++;
+        s->tickets[tk] = Ticket{group, now_ns(), 1};
+        s->queue.push_back(tk);
+        *ticket = tk;
+    }
+    s->cv_sched.notify_one();
+    return GEN_OK;
+}
+
+int gen_server_wait(gen_server *s, uint64_t ticket, int64_t timeout_us)
+{
+    if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return sfail(GEN_ENOTFOUND, "unknown ticket");
+    auto gi = s->groups.find(it->second.group);
+    if (it->second.status == 1 && gi != s->groups.end()) {
+        Group &g = *gi->second;            // stays alive while waiters > 0 (close waits)
+        const auto deadline = Clock::now() + std::chrono::microseconds(timeout_us < 0 ? 0 : timeout_us);
+        g.waiters += 1;
+        bool timed_out = false;
+        while (it->second.status == 1) {
+            if (timeout_us < 0) {
+                g.cv.wait(lk);
+            } else if (g.cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+                timed_out = it->second.status == 1;
+                break;
+            }
+        }
+        g.waiters -= 1;
+        if (g.closing) g.cv.notify_all();
+        if (timed_out) return GEN_EBUSY;
+    }
+    const int st = it->second.status;
+    s->tickets.erase(it);
+    if (st == 1) return sfail(GEN_ENOTFOUND, "group closed");
+    if (st != 0) return sfail(st, s->error.empty() ? "request failed" : s->error);
+    return GEN_OK;
+}
+
+int gen_server_close(gen_server *s, uint64_t group)
+{
+    if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->groups.find(group);
+    if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
+    Group &g = *it->second;
+    g.closing = true;
+    for (auto &[tk, t] : s->tickets)
+        if (t.group == group && t.status == 1) {
+            const bool queued = std::find(s->queue.begin(), s->queue.end(), tk) != s->queue.end();
+            if (queued) t.status = GEN_ENOTFOUND;
+        }
+    g.cv.notify_all();
+    while (g.busy || g.waiters > 0) g.cv.wait(lk);
+    const uint64_t sz[5] = {g.sz_state, g.sz_obs, g.sz_act, g.sz_act, g.sz_done};
+    const uint64_t o[5] = {g.off_state, g.off_obs, g.off_act, g.off_rew, g.off_done};
+    for (int j = 0; j < 5; ++j) s->alloc.release(o[j], sz[j]);
+    gen_pool_destroy(g.pool);
+    s->groups.erase(it);
+    return GEN_OK;
+}
+
+int gen_server_report(gen_server *s, gen_server_stats *out, int32_t reset)
+{
+    if (s == nullptr || out == nullptr) return sfail(GEN_EINVAL, "server and out are required");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof *out);
+    out->requests = s->st_requests;
+    out->frames = s->st_frames;
+    out->launches = s->st_launches;
+    out->groups_open = s->groups.size();
+    out->groups_refused = s->st_refused;
+    out->arena_bytes = s->arena_bytes;
+    out->bytes_in_use = s->alloc.used();
+    out->envs_per_launch = s->st_launches ? (double)s->st_launch_envs / (double)s->st_launches : 0.0;
+    if (!s->lat_us.empty()) {
+        std::vector<float> v = s->lat_us;
+        const size_t i50 = v.size() / 2, i99 = std::min(v.size() - 1, (size_t)(v.size() * 0.99));
+        std::nth_element(v.begin(), v.begin() + i50, v.end());
+        out->lat_p50_us = v[i50];
+        std::nth_element(v.begin(), v.begin() + i99, v.end());
+        out->lat_p99_us = v[i99];
+        double sum = 0;
+        for (float x : v) sum += x;
+        out->lat_mean_us = sum / (double)v.size();
+    }
+    if (reset) {
+        s->st_requests = s->st_frames = s->st_launches = s->st_launch_envs = s->st_refused = 0;
+        s->lat_us.clear();
+    }
+    return GEN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- load generator
+namespace {
+
+struct ClientGroup {
+    uint64_t id = 0;
+    uint64_t ticket = 0;
+    bool outstanding = false;
+    int32_t steps = 0;
+    int32_t spec_begin = 0, n_envs = 0;
+    uint64_t env_base = 0;
+};
+
+}  // namespace
+
+extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups_per_client, const int32_t *h_group_envs,
+                                const gen_env_spec *h_specs, const gen_params *common, uint64_t seed,
+                                uint64_t actor_seed, const double *h_gaps_us, int32_t gaps_per_client,
+                                int64_t duration_us, int32_t steps_per_group, gen_server_stats *out)
+{
+    if (s == nullptr || out == nullptr || h_group_envs == nullptr || h_specs == nullptr || h_gaps_us == nullptr)
+        return sfail(GEN_EINVAL, "missing argument");
+    if (n_clients < 1 || groups_per_client < 1 || gaps_per_client < 1 || duration_us < 1)
+        return sfail(GEN_EINVAL, "bad client configuration");
+    const int32_t n_groups = n_clients * groups_per_client;
+    std::vector<int32_t> spec_begin((size_t)n_groups + 1, 0);
+    for (int32_t g = 0; g < n_groups; ++g) spec_begin[(size_t)g + 1] = spec_begin[(size_t)g] + h_group_envs[g];
+    const uint64_t total_envs = (uint64_t)spec_begin[(size_t)n_groups];
+    std::atomic<int> failure{0};
+    std::atomic<uint64_t> reopen_base{total_envs};
+    std::vector<std::vector<ClientGroup>> cg((size_t)n_clients);
+    // open every group first (blocking map generation), then measure
+    for (int32_t c = 0; c < n_clients && !failure; ++c) {
+        for (int32_t k = 0; k < groups_per_client; ++k) {
+            const int32_t g = c * groups_per_client + k;
+            ClientGroup x;
+            x.spec_begin = spec_begin[(size_t)g];
+            x.n_envs = h_group_envs[g];
+            x.env_base = (uint64_t)x.spec_begin;
+            const int rc = gen_server_open(s, seed, x.env_base, x.n_envs, h_specs + x.spec_begin, common, 1,
+                                           actor_seed, &x.id);
+            if (rc != GEN_OK) { failure = rc; break; }
+            cg[(size_t)c].push_back(x);
+        }
+    }
+    if (failure) return failure.load();
+    gen_server_stats tmp;
+    gen_server_report(s, &tmp, 1);
+    const auto t0 = Clock::now();
+    const auto t_end = t0 + std::chrono::microseconds(duration_us);
+    auto client = [&](int32_t c) {
+        auto &groups = cg[(size_t)c];
+        auto next = t0;
+        int32_t gi = 0, k = 0;
+        while (!failure) {
+            next += std::chrono::nanoseconds((int64_t)(h_gaps_us[(size_t)c * gaps_per_client + (k % gaps_per_client)] * 1000.0));
+            ++k;
+            if (next >= t_end) break;
+            std::this_thread::sleep_until(next);
+            ClientGroup &x = groups[(size_t)gi];
+            gi = (gi + 1) % (int32_t)groups.size();
+            if (x.outstanding) {
+                const int rc = gen_server_wait(s, x.ticket, -1);
+                if (rc != GEN_OK) { failure = rc; break; }
+                x.outstanding = false;
+                x.steps += 1;
+            }
+            if (steps_per_group > 0 && x.steps >= steps_per_group) {
+                if (gen_server_close(s, x.id) != GEN_OK) { failure = GEN_EHIP; break; }
+                x.env_base = reopen_base.fetch_add((uint64_t)x.n_envs);
+                const int rc = gen_server_open(s, seed, x.env_base, x.n_envs, h_specs + x.spec_begin, common, 1,
+                                               actor_seed, &x.id);
+                if (rc != GEN_OK) { failure = rc; break; }
+                x.steps = 0;
+            }
+            if (gen_server_submit(s, x.id, &x.ticket) != GEN_OK) { failure = GEN_EHIP; break; }
+            x.outstanding = true;
+        }
+        for (auto &x : groups)
+            if (x.outstanding) { gen_server_wait(s, x.ticket, -1); x.outstanding = false; }
+    };
+    std::vector<std::thread> th;
+    th.reserve((size_t)n_clients);
+    for (int32_t c = 0; c < n_clients; ++c) th.emplace_back(client, c);
+    for (auto &t : th) t.join();
+    const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
+    gen_server_report(s, out, 1);
+    out->wall_s = secs;
+    for (auto &groups : cg)
+        for (auto &x : groups) gen_server_close(s, x.id);
+    if (failure) return failure.load();
+    return GEN_OK;
+}

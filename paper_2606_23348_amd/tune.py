@@ -1,0 +1,109 @@
+"""Packing autotuner for batched pools.
+
+For a pool's mix of shapes and modes it times every candidate packing
+(envs per workgroup, persistent grid size, work order) on a scratch copy of
+the pool and keeps the fastest.  A candidate is accepted only if, from the
+same reset, a few steps under it leave the state, observations, actions,
+rewards and done flags bit-identical to the default packing.  Results are
+cached per (GPU architecture, pool signature) in a JSON file.
+
+    best, table = tune(specs, common, seed=4, actor_seed=1004)
+    pool.set_tuning(**best)
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from . import GenError, Pool, SPEC_FIELDS
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2606_23348_amd", "pool_tuning.json")
+
+
+def candidates(n_cus: int) -> list:
+    out = []
+    for order in (0, 1):
+        for wpg in (1, 2, 4):
+            for grid in (0, 4 * n_cus, 8 * n_cus, 16 * n_cus):
+                out.append({"waves_per_group": wpg, "grid": grid, "order": order})
+    return out
+
+
+def signature(specs: dict) -> str:
+    """Histogram of (H, W, mode, P, cities, spawn distance) buckets."""
+    rows = np.stack([np.asarray(specs[k], np.int64) for k in SPEC_FIELDS], axis=1)
+    uniq, counts = np.unique(rows, axis=0, return_counts=True)
+    h = hashlib.sha256(uniq.tobytes() + counts.tobytes()).hexdigest()[:16]
+    return f"n{rows.shape[0]}-{h}"
+
+
+def _digest(pool: Pool) -> str:
+    h = hashlib.sha256()
+    for t in (pool.buf, pool.obs, pool.actions, pool.rewards, pool.dones):
+        if t is not None:
+            h.update(t.cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def _run_from_reset(pool: Pool, actor_seed: int, steps: int, stream):
+    pool.reset(actor_seed=actor_seed, stream=stream)
+    for _ in range(steps):
+        pool.step(actor_seed=actor_seed, stream=stream)
+
+
+def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: int = 10, warmup: int = 2,
+         verify_steps: int = 3, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+         cands: list | None = None):
+    """Returns (best tuning dict, {candidate: mean step microseconds or None})."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    sig = signature(specs)
+    key = f"{arch}/{sig}"
+    if cache_path and not force and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]["best"], cache[key]["table"]
+    n_cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cands = cands or candidates(n_cus)
+    stream = torch.cuda.current_stream()
+    pool = Pool(specs, common, seed=seed)
+    _run_from_reset(pool, actor_seed, verify_steps, stream)
+    ref = _digest(pool)
+    table = {}
+    best, best_us = None, float("inf")
+    for c in cands:
+        name = json.dumps(c, sort_keys=True)
+        try:
+            pool.set_tuning(**c, stream=stream)
+        except GenError:
+            table[name] = None                       # does not fit (LDS)
+            continue
+        _run_from_reset(pool, actor_seed, verify_steps, stream)
+        if _digest(pool) != ref:
+            raise RuntimeError(f"packing {c} changed the results")
+        for _ in range(warmup):
+            pool.step(actor_seed=actor_seed, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            pool.step(actor_seed=actor_seed, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / steps
+        table[name] = us
+        if us < best_us:
+            best, best_us = c, us
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = {"best": best, "table": table, "best_us": best_us}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return best, table

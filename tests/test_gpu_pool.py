@@ -116,7 +116,7 @@ def _digest(gen, specs, tuning, steps=25):
 
 
 def test_pool_results_independent_of_packing(gen):
-    specs = random_specs(700, 11)
+    specs = random_specs(700, 11, 3, 24)        # 4 waves x the largest env fit in 64 KiB of LDS
     ref = _digest(gen, specs, dict(waves_per_group=1, grid=0, order=0))
     for tun in (dict(waves_per_group=2, grid=0, order=0), dict(waves_per_group=4, grid=0, order=1),
                 dict(waves_per_group=1, grid=37, order=1), dict(waves_per_group=2, grid=100, order=0)):

@@ -1,0 +1,151 @@
+"""The served form: continuous batching over a device arena.
+
+Each group's results must be the same whether its steps ran alone or
+batched with other groups' steps, and must match the CPU oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+KEYS = ("owner", "army", "type", "turn", "episode", "alive", "finished", "gpos")
+WAIT_US = 20_000_000          # every wait is bounded
+
+
+@pytest.fixture(scope="module")
+def gen():
+    import torch
+    import paper_2606_23348_amd as g
+    assert torch.cuda.is_available()
+    g.lib()
+    return g
+
+
+def group_specs(n, seed, lo=6, hi=20):
+    rng = np.random.default_rng(seed)
+    H, W = rng.integers(lo, hi + 1, n), rng.integers(lo, hi + 1, n)
+    mode = rng.integers(0, 3, n)
+    P = np.where(mode == 0, 2, np.where(mode == 1, 4, rng.integers(2, 7, n)))
+    cmax = np.minimum(H * W // 8, 8)
+    return {"H": H, "W": W, "mode": mode, "P": P, "cities_min": cmax // 2, "cities_max": cmax,
+            "min_general_dist": np.minimum((H + W) // 4, 8)}
+
+
+def common(gen):
+    return gen.make_params(0, 2, mountain_thresh=workloads.mountain_thresh(1, 5), city_army_min=40,
+                           city_army_max=50, auto_reset=1)
+
+
+def snapshot(srv, gid, specs):
+    b = srv.buffers(gid)
+    st = [srv.get_env(gid, e, int(specs["H"][e]), int(specs["W"][e]), int(specs["P"][e])) for e in range(b["n_envs"])]
+    return st, b["obs"].cpu().numpy(), b["actions"].cpu().numpy(), b["rewards"].cpu().numpy(), b["dones"].cpu().numpy()
+
+
+def test_server_mix_vs_alone(gen):
+    specs = [group_specs(n, 100 + i) for i, n in enumerate((40, 7, 130, 64, 1, 90))]
+    bases = np.cumsum([0] + [len(s["H"]) for s in specs])
+    T = 25
+    results = {}
+    for mode in ("alone", "mixed"):
+        srv = gen.Server(256 << 20, n_launch_streams=2)
+        gids = [srv.open(s, seed=17, env_base=int(bases[i]), common=common(gen), actor_seed=23)
+                for i, s in enumerate(specs)]
+        for t in range(T):
+            if mode == "alone":
+                for g in gids:
+                    assert srv.wait(srv.submit(g), WAIT_US) == gen.GEN_OK
+            else:
+                tickets = [srv.submit(g) for g in gids]
+                for tk in tickets:
+                    assert srv.wait(tk, WAIT_US) == gen.GEN_OK
+        results[mode] = [snapshot(srv, g, s) for g, s in zip(gids, specs)]
+        rep = srv.report()
+        assert rep["requests"] == T * len(gids)
+        if mode == "mixed":
+            assert rep["envs_per_launch"] > max(len(s["H"]) for s in specs)   # steps of several groups per launch
+        srv.close_server()
+    for (sa, oa, aa, ra, da), (sb, ob, ab, rb, db) in zip(results["alone"], results["mixed"]):
+        for x, y in zip(sa, sb):
+            for k in KEYS:
+                assert np.array_equal(x[k], y[k])
+        for x, y in ((oa, ob), (aa, ab), (ra, rb), (da, db)):
+            assert np.array_equal(x, y)
+    # and the same as independent oracle runs (first and last env of every group)
+    for i, s in enumerate(specs):
+        for e in {0, len(s["H"]) - 1}:
+            cfg = oracle.Config(H=int(s["H"][e]), W=int(s["W"][e]), mode=int(s["mode"][e]), P=int(s["P"][e]),
+                                mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=int(s["cities_min"][e]),
+                                cities_max=int(s["cities_max"][e]), city_army_min=40, city_army_max=50,
+                                min_general_dist=int(s["min_general_dist"][e]), auto_reset=1, seed=17,
+                                env_base=int(bases[i]) + e)
+            ost, _ = oracle.reset(cfg, 1)
+            for t in range(T):
+                oracle.step(cfg, ost, oracle.sample(cfg, ost, 23, t))
+            got = results["mixed"][i][0][e]
+            for k in KEYS:
+                assert np.array_equal(got[k], ost[k]), (i, e, k)
+
+
+def test_server_budget_admission(gen):
+    specs = group_specs(200, 5, 20, 24)
+    srv = gen.Server(24 << 20, n_launch_streams=1)
+    opened = []
+    with pytest.raises(gen.GenError) as ei:
+        for i in range(100):
+            opened.append(srv.open(specs, seed=1, env_base=200 * i, common=common(gen), actor_seed=2))
+    assert ei.value.code == gen.GEN_EBUDGET
+    assert 1 <= len(opened) < 100
+    rep = srv.report()
+    assert rep["groups_refused"] == 1 and rep["bytes_in_use"] <= rep["arena_bytes"]
+    srv.close(opened[0])                   # memory frees up -> the next open is admitted
+    g = srv.open(specs, seed=1, env_base=99999, common=common(gen), actor_seed=2)
+    assert srv.wait(srv.submit(g), WAIT_US) == gen.GEN_OK
+    with pytest.raises(gen.GenError):
+        srv.submit(opened[0])              # closed group
+    srv.close_server()
+
+
+def test_server_concurrent_clients(gen):
+    srv = gen.Server(128 << 20, n_launch_streams=2)
+    specs = group_specs(96, 8)
+    gids = [srv.open(specs, seed=3, env_base=96 * i, common=common(gen), actor_seed=4) for i in range(12)]
+    errors = []
+
+    def client(g):
+        try:
+            for _ in range(40):
+                if srv.wait(srv.submit(g), WAIT_US) != gen.GEN_OK:
+                    errors.append("timeout")
+                    return
+        except Exception as exc:  # pragma: no cover - reported below
+            errors.append(repr(exc))
+
+    th = [threading.Thread(target=client, args=(g,)) for g in gids]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=60)
+    assert not errors and not any(t.is_alive() for t in th)
+    rep = srv.report()
+    assert rep["requests"] == 12 * 40 and rep["frames"] == 12 * 40 * 96
+    assert rep["launches"] <= rep["requests"]
+    assert 0 < rep["lat_p50_us"] <= rep["lat_p99_us"]
+    srv.close_server()
+
+
+def test_server_native_clients(gen):
+    srv = gen.Server(512 << 20, n_launch_streams=2)
+    n_clients, gpc = 16, 2
+    sizes = workloads.group_sizes(5, n_clients * gpc, 64, 256)
+    specs = workloads.mixed_specs(int(sizes.sum()), 5)
+    gaps = np.stack([workloads.arrival_gaps(2005, c, 64, 4000.0) * 1e6 for c in range(n_clients)])
+    rep = srv.drive(sizes, specs, seed=5, actor_seed=1005, gaps_us=gaps, duration_s=0.5, steps_per_group=40,
+                    common=common(gen))
+    assert rep["requests"] > 100 and rep["frames"] > 0 and rep["wall_s"] > 0.4
+    assert 0 < rep["lat_p50_us"] <= rep["lat_p99_us"]
+    assert srv.report()["groups_open"] == 0
+    srv.close_server()
