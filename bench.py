@@ -95,6 +95,134 @@ def copy_ceiling_gbs(torch, n_bytes: int = 1 << 30, reps: int = 10) -> float:
     return gbs
 
 
+def pool_bytes_per_frame(specs) -> float:
+    """Mean algorithmic bytes per frame of the pooled step (same accounting as
+    step_bytes, per env shape; the scalar record also carries the step
+    counter, so 14 live bytes are written)."""
+    HW = specs["H"].astype(np.int64) * specs["W"].astype(np.int64)
+    P = specs["P"].astype(np.int64)
+    read = HW * 6 + 32 + 4 * P + 32          # + the env's 32-byte descriptor
+    write = HW * 5 + P * 8 * HW + 4 * P + 1 + 14 + 4 * P
+    return float((read + write).mean())
+
+
+def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
+    """The mixed pool in one launch per step, replayed from a captured graph,
+    against one plain launch per (H, W, mode) bucket over the same envs."""
+    from paper_2606_23348_amd import tune as tuner
+    wl = workloads.C4
+    specs = workloads.mixed_specs(wl.n_envs, wl.seed)
+    common = gen.make_params(0, 2, mountain_thresh=wl.thresh, city_army_min=wl.city_army_min,
+                             city_army_max=wl.city_army_max, auto_reset=wl.auto_reset)
+    best, table = ({"waves_per_group": 1, "grid": 0, "order": 0}, {})
+    if tune_it:
+        best, table = tuner.tune(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, steps=8, cache_path=None)
+    pool = gen.Pool(specs, common, seed=wl.seed)
+    s = torch.cuda.Stream()
+    K = 10
+    with torch.cuda.stream(s):
+        pool.set_tuning(**best, stream=s)
+        pool.reset(actor_seed=wl.actor_seed, stream=s)
+        pool.capture(K, wl.actor_seed, s)
+        pool.replay(s)
+        s.synchronize()
+        reps = max(1, steps // K)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            pool.replay(s)
+        e1.record(s)
+        s.synchronize()
+    step_s = e0.elapsed_time(e1) / 1e3 / (reps * K)
+    bpf = pool_bytes_per_frame(specs)
+    achieved = bpf * wl.n_envs / step_s / 1e9
+    del pool
+    # baseline: each (H, W, mode, P) bucket as its own plain batch, one launch each per step
+    keys = np.stack([specs["H"], specs["W"], specs["mode"], specs["P"]], 1)
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    batches = []
+    for bi, (H, W, mode, P) in enumerate(uniq):
+        n = int((inv == bi).sum())
+        first = int(np.flatnonzero(inv == bi)[0])
+        prm = gen.make_params(int(mode), int(P), mountain_thresh=wl.thresh, cities_min=int(specs["cities_min"][first]),
+                              cities_max=int(specs["cities_max"][first]),
+                              min_general_dist=int(specs["min_general_dist"][first]),
+                              city_army_min=wl.city_army_min, city_army_max=wl.city_army_max, auto_reset=1)
+        b = gen.Batch(n, int(H), int(W), int(mode), prm, seed=wl.seed, env_base=first)
+        b.sample(wl.actor_seed, 0)
+        batches.append(b)
+    bsteps = 5
+    for b in batches:
+        b.step_sample(wl.actor_seed, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(bsteps):
+        for b in batches:
+            b.step_sample(wl.actor_seed, t + 2)
+    torch.cuda.synchronize()
+    bucket_s = (time.perf_counter() - t0) / bsteps
+    del batches
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "n_envs": wl.n_envs, "frames_per_s": wl.n_envs / step_s,
+            "ms_per_step": step_s * 1e3, "graph_steps": K, "tuning": best,
+            "tuning_candidates": len(table),
+            "per_bucket_plain": {"buckets": int(len(uniq)), "frames_per_s": wl.n_envs / bucket_s,
+                                 "ms_per_step": bucket_s * 1e3},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": bpf}}
+
+
+def run_served_c2(gen, torch, duration_s: float) -> dict:
+    """The headline workload served: its 65,536 envs as 256 groups of 256,
+    one closed-loop client per group issuing back-to-back step requests."""
+    wl = workloads.C2
+    n_clients, per = 256, 256
+    specs = {"H": np.full(n_clients * per, wl.H), "W": np.full(n_clients * per, wl.W),
+             "mode": np.full(n_clients * per, wl.mode), "P": np.full(n_clients * per, wl.P),
+             "cities_min": np.full(n_clients * per, wl.cities_min),
+             "cities_max": np.full(n_clients * per, wl.cities_max),
+             "min_general_dist": np.full(n_clients * per, wl.min_general_dist)}
+    common = gen.make_params(0, 2, **wl.params())
+    srv = gen.Server(3 << 30, n_launch_streams=2)
+    gaps = np.zeros((n_clients, 1))
+    rep = srv.drive(np.full(n_clients, per), specs, seed=wl.seed, actor_seed=wl.actor_seed, gaps_us=gaps,
+                    duration_s=duration_s, steps_per_group=0, common=common)
+    srv.close_server()
+    del srv
+    torch.cuda.empty_cache()
+    return {"workload": "served-" + wl.name + " (256 groups x 256 envs, 256 closed-loop clients)",
+            "frames_per_s": rep["frames"] / rep["wall_s"], "requests": rep["requests"],
+            "lat_p50_us": rep["lat_p50_us"], "lat_p99_us": rep["lat_p99_us"],
+            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
+
+
+def run_served_mix(gen, torch, duration_s: float) -> dict:
+    """256 clients x 8 groups of 64..2,048 envs with the pooled mix of shapes
+    and modes; Poisson arrivals at 4,000 requests/s per client, closed loop
+    per group; groups end after 1,000 steps and are replaced."""
+    wl = workloads.C5
+    n_groups = wl.n_streams * wl.groups_per_stream
+    sizes = workloads.group_sizes(wl.seed, n_groups, wl.batch_min, wl.batch_max)
+    specs = workloads.mixed_specs(int(sizes.sum()), wl.seed)
+    common = gen.make_params(0, 2, mountain_thresh=workloads.mountain_thresh(1, 5), city_army_min=40,
+                             city_army_max=50, auto_reset=1)
+    gaps = np.stack([workloads.arrival_gaps(wl.arrival_seed, c, 4096, wl.rate_per_stream) * 1e6
+                     for c in range(wl.n_streams)])
+    arena = 32 << 30
+    srv = gen.Server(arena, n_launch_streams=2)
+    rep = srv.drive(sizes, specs, seed=wl.seed, actor_seed=wl.actor_seed, gaps_us=gaps, duration_s=duration_s,
+                    steps_per_group=wl.steps_per_group, common=common)
+    srv.close_server()
+    del srv
+    torch.cuda.empty_cache()
+    return {"workload": wl.name + f" ({wl.n_streams} clients x {wl.groups_per_stream} groups of "
+                                  f"{wl.batch_min}-{wl.batch_max} envs, Poisson {wl.rate_per_stream:.0f} req/s each)",
+            "resident_envs": int(sizes.sum()), "arena_gb": arena / 2 ** 30,
+            "frames_per_s": rep["frames"] / rep["wall_s"], "requests": rep["requests"],
+            "lat_p50_us": rep["lat_p50_us"], "lat_p99_us": rep["lat_p99_us"],
+            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
+
+
 def cpu_baseline(wl, n_envs: int, n_steps: int) -> dict:
     import oracle
     cfg = oracle.Config(H=wl.H, W=wl.W, mode=wl.mode, P=wl.P, seed=wl.seed, **wl.params())
@@ -118,6 +246,10 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run N copies of 1 GiB (counter calibration run) and exit")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain workload only (no served, pooled or copy-ceiling legs)")
+    ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -194,8 +326,15 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_env<STEP, actor fused> (gen_step_sample)",
                      "algorithmic_bytes_per_frame": by["step"],
-                     "frames_per_launch": E, "copy_ceiling_gbs": copy_ceiling_gbs(torch)},
+                     "frames_per_launch": E},
     }
+    if not args.no_extras:
+        del b
+        torch.cuda.empty_cache()
+        out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(torch)
+        out["served"] = run_served_c2(gen, torch, args.served_seconds)
+        out["pool"] = run_pool(gen, torch, 200, not args.no_tune)
+        out["served_mix"] = run_served_mix(gen, torch, args.served_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_envs, args.cpu_steps)
     print(json.dumps(out), flush=True)

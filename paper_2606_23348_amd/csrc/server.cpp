@@ -496,6 +496,8 @@ int gen_server_report(gen_server *s, gen_server_stats *out, int32_t reset)
 // ---------------------------------------------------------------- load generator
 namespace {
 
+constexpr int64_t kDriveWaitUs = 30000000;   // a request taking longer than this fails the run
+
 struct ClientGroup {
     uint64_t id = 0;
     uint64_t ticket = 0;
@@ -554,7 +556,7 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
             ClientGroup &x = groups[(size_t)gi];
             gi = (gi + 1) % (int32_t)groups.size();
             if (x.outstanding) {
-                const int rc = gen_server_wait(s, x.ticket, -1);
+                const int rc = gen_server_wait(s, x.ticket, kDriveWaitUs);
                 if (rc != GEN_OK) { failure = rc; break; }
                 x.outstanding = false;
                 x.steps += 1;
@@ -571,7 +573,7 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
             x.outstanding = true;
         }
         for (auto &x : groups)
-            if (x.outstanding) { gen_server_wait(s, x.ticket, -1); x.outstanding = false; }
+            if (x.outstanding) { gen_server_wait(s, x.ticket, kDriveWaitUs); x.outstanding = false; }
     };
     std::vector<std::thread> th;
     th.reserve((size_t)n_clients);
