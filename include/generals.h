@@ -219,6 +219,8 @@ typedef struct gen_pool_info {
     uint64_t state_bytes;       /* device state buffer to pass to gen_pool_reset */
     uint64_t obs_bytes;         /* ragged observation buffer (each env block 16-byte aligned) */
     uint64_t n_actions;         /* int32 entries of the ragged actions and rewards buffers (sum of P) */
+    uint64_t work_list_off;     /* the work list inside the state buffer: the only bytes */
+    uint64_t work_list_bytes;   /* of the state that depend on the packing (gen_pool_tuning) */
 } gen_pool_info;
 
 /* Packing of envs onto the GPU (chosen by the autotuner):

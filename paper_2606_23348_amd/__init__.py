@@ -58,7 +58,8 @@ class gen_env_spec(ctypes.Structure):
 
 class gen_pool_info(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("max_cells", ctypes.c_int32), ("state_bytes", ctypes.c_uint64),
-                ("obs_bytes", ctypes.c_uint64), ("n_actions", ctypes.c_uint64)]
+                ("obs_bytes", ctypes.c_uint64), ("n_actions", ctypes.c_uint64),
+                ("work_list_off", ctypes.c_uint64), ("work_list_bytes", ctypes.c_uint64)]
 
 
 class gen_pool_tuning(ctypes.Structure):
@@ -394,6 +395,20 @@ class Pool:
         hs = _host_struct(h)
         _check(lib().gen_pool_get_env(self.handle, e, ctypes.byref(hs), _stream(stream)))
         return h
+
+    def digest(self) -> str:
+        """SHA-256 of every output and of the state except the work list
+        (the one part of the state that depends on the packing)."""
+        import hashlib
+        h = hashlib.sha256()
+        buf = self.buf.cpu().numpy()
+        a, b = self.info.work_list_off, self.info.work_list_off + self.info.work_list_bytes
+        h.update(buf[:a].tobytes())
+        h.update(buf[b:].tobytes())
+        for t in (self.obs, self.actions, self.rewards, self.dones):
+            if t is not None:
+                h.update(t.cpu().numpy().tobytes())
+        return h.hexdigest()
 
     def env_obs(self, e: int):
         H, W, P = (int(self.specs[k][e]) for k in ("H", "W", "P"))

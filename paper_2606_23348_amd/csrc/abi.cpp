@@ -514,6 +514,8 @@ int gen_pool_query(const gen_pool *pool, gen_pool_info *out)
     out->state_bytes = pool->state_bytes;
     out->obs_bytes = pool->obs_bytes;
     out->n_actions = pool->n_actions;
+    out->work_list_off = pool->off_order;
+    out->work_list_bytes = (uint64_t)pool->n * sizeof(uint32_t);
     return ok();
 }
 

@@ -40,14 +40,6 @@ def signature(specs: dict) -> str:
     return f"n{rows.shape[0]}-{h}"
 
 
-def _digest(pool: Pool) -> str:
-    h = hashlib.sha256()
-    for t in (pool.buf, pool.obs, pool.actions, pool.rewards, pool.dones):
-        if t is not None:
-            h.update(t.cpu().numpy().tobytes())
-    return h.hexdigest()
-
-
 def _run_from_reset(pool: Pool, actor_seed: int, steps: int, stream):
     pool.reset(actor_seed=actor_seed, stream=stream)
     for _ in range(steps):
@@ -72,7 +64,7 @@ def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: in
     stream = torch.cuda.current_stream()
     pool = Pool(specs, common, seed=seed)
     _run_from_reset(pool, actor_seed, verify_steps, stream)
-    ref = _digest(pool)
+    ref = pool.digest()
     table = {}
     best, best_us = None, float("inf")
     for c in cands:
@@ -83,7 +75,7 @@ def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: in
             table[name] = None                       # does not fit (LDS)
             continue
         _run_from_reset(pool, actor_seed, verify_steps, stream)
-        if _digest(pool) != ref:
+        if pool.digest() != ref:
             raise RuntimeError(f"packing {c} changed the results")
         for _ in range(warmup):
             pool.step(actor_seed=actor_seed, stream=stream)
