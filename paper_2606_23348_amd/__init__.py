@@ -286,8 +286,9 @@ class Batch:
         lay = gen_layout(n_envs, H, W, mode, params, seed)
         P = lay.n_players
         self.n_envs, self.H, self.W, self.mode, self.P = n_envs, H, W, mode, P
-        self.buf = torch.empty(lay.bytes, dtype=torch.uint8, device=device)
-        self.obs = torch.empty((n_envs, P, 8, H, W), dtype=torch.uint8, device=device) if with_obs else None
+        # zero-filled, so alignment padding the library never writes is deterministic
+        self.buf = torch.zeros(lay.bytes, dtype=torch.uint8, device=device)
+        self.obs = torch.zeros((n_envs, P, 8, H, W), dtype=torch.uint8, device=device) if with_obs else None
         self.actions = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
         self.rewards = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
         self.dones = torch.zeros(n_envs, dtype=torch.uint8, device=device)
@@ -352,8 +353,9 @@ class Pool:
         self.obs_off = np.zeros(self.n, np.uint64)
         self.act_off = np.zeros(self.n, np.uint32)
         _check(lib().gen_pool_offsets(self.handle, self.obs_off.ctypes.data, self.act_off.ctypes.data))
-        self.buf = torch.empty(info.state_bytes, dtype=torch.uint8, device=device)
-        self.obs = torch.empty(max(info.obs_bytes, 16), dtype=torch.uint8, device=device) if with_obs else None
+        # zero-filled, so alignment padding the library never writes is deterministic
+        self.buf = torch.zeros(info.state_bytes, dtype=torch.uint8, device=device)
+        self.obs = torch.zeros(max(info.obs_bytes, 16), dtype=torch.uint8, device=device) if with_obs else None
         self.actions = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
         self.rewards = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
         self.dones = torch.zeros(self.n, dtype=torch.uint8, device=device)
