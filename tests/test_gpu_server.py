@@ -40,9 +40,14 @@ def common(gen):
 
 
 def snapshot(srv, gid, specs):
+    """Every env's state and the bytes the step defines (each env's
+    observation block, not the alignment padding between blocks)."""
     b = srv.buffers(gid)
     st = [srv.get_env(gid, e, int(specs["H"][e]), int(specs["W"][e]), int(specs["P"][e])) for e in range(b["n_envs"])]
-    return st, b["obs"].cpu().numpy(), b["actions"].cpu().numpy(), b["rewards"].cpu().numpy(), b["dones"].cpu().numpy()
+    obs = b["obs"].cpu().numpy()
+    blocks = np.concatenate([obs[int(b["obs_off"][e]):int(b["obs_off"][e]) + int(specs["P"][e]) * 8 *
+                                 int(specs["H"][e]) * int(specs["W"][e])] for e in range(b["n_envs"])])
+    return st, blocks, b["actions"].cpu().numpy(), b["rewards"].cpu().numpy(), b["dones"].cpu().numpy()
 
 
 def test_server_mix_vs_alone(gen):
