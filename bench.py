@@ -95,6 +95,27 @@ def copy_ceiling_gbs(torch, n_bytes: int = 1 << 30, reps: int = 10) -> float:
     return gbs
 
 
+def run_step_alone(b, wl, torch, stream, steps: int, first_step: int) -> dict:
+    """gen_step by itself with the actions already in HBM: each step's
+    actions come from a separate gen_sample_actions launch that lies
+    outside the events timing the step."""
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for t in range(steps):
+        b.sample(wl.actor_seed, first_step + t)
+        ev0[t].record(stream)
+        b.step()
+        ev1[t].record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev0[t].elapsed_time(ev1[t]) for t in range(steps)])
+    by = step_bytes(wl)
+    alone = by["step"] - 4 * wl.P          # no next-step actions written
+    return {"kernel": "k_env<STEP> (gen_step)", "steps": steps, "step_kernel_ms_mean": float(ms.mean()),
+            "step_kernel_ms_p50": float(np.percentile(ms, 50)), "step_kernel_ms_p99": float(np.percentile(ms, 99)),
+            "frames_per_s": b.n_envs / (float(ms.mean()) / 1e3),
+            "achieved_gbs": alone * b.n_envs / (float(ms.mean()) / 1e3) / 1e9, "algorithmic_bytes_per_frame": alone}
+
+
 def pool_bytes_per_frame(specs) -> float:
     """Mean algorithmic bytes per frame of the pooled step (same accounting as
     step_bytes, per env shape; the scalar record also carries the step
@@ -329,6 +350,7 @@ def main() -> int:
                      "frames_per_launch": E},
     }
     if not args.no_extras:
+        out["step_alone"] = run_step_alone(b, wl, torch, stream, min(K, 1000), W + K + 1)
         del b
         torch.cuda.empty_cache()
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(torch)

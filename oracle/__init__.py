@@ -39,7 +39,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-Werror",
-                               "-shared", "-fPIC", "-o", tmp, _SRC])
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -76,6 +76,9 @@ def lib():
         _lib.orc_scoreboard_batch.argtypes = [vp, i32, vp, vp, vp]
         _lib.orc_sample_batch.argtypes = [vp, i32, vp, u64, u64, vp]
         _lib.orc_run.argtypes = [vp, i32, vp, u64, u64, i32, vp, vp, vp, vp]
+        _lib.orc_fmem_bytes.argtypes = []
+        _lib.orc_fmem_bytes.restype = ctypes.c_int64
+        _lib.orc_features_batch.argtypes = [vp, i32, vp, vp, vp]
         for f in ("orc_reset_batch", "orc_step_batch", "orc_observe_batch",
                   "orc_scoreboard_batch", "orc_sample_batch", "orc_run"):
             getattr(_lib, f).restype = ctypes.c_int
@@ -197,6 +200,26 @@ def run(cfg: Config, st: dict, seed_act: int, step0: int, n_steps: int):
     _check(lib().orc_run(ctypes.byref(c), E, ctypes.byref(b), seed_act, step0, n_steps,
                          _ptr(act), _ptr(rew), _ptr(done), _ptr(obs)))
     return act, rew, done, obs
+
+
+FEAT_CHANNELS = 38
+
+
+def feature_memory(E: int) -> np.ndarray:
+    """Zero-filled per-env memory of the 38-channel features (one episode's
+    running masks and the last 8 frames)."""
+    return np.zeros((E, int(lib().orc_fmem_bytes())), np.uint8)
+
+
+def features(cfg: Config, st: dict, mem: np.ndarray) -> np.ndarray:
+    """Record the current frame of every env into `mem` and return the
+    38-channel features float32 [E][P][38][H][W] (Appendix A, reading R17)."""
+    E = st["turn"].shape[0]
+    assert mem.shape[0] == E and mem.flags["C_CONTIGUOUS"]
+    out = np.zeros((E, cfg.P, FEAT_CHANNELS, cfg.H, cfg.W), np.float32)
+    c, b = cfg._c(), _batch(st)
+    _check(lib().orc_features_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(mem), _ptr(out)))
+    return out
 
 
 def philox(ctr, key) -> np.ndarray:

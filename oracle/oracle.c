@@ -10,7 +10,7 @@
  * host-state format (plain arrays) and the seeds.
  *
  * The paper leaves many details open.  Every such gap is filled by a numbered
- * reading (R1..R16) that the HIP path follows too; the readings are listed,
+ * reading (R1..R17) that the HIP path follows too; the readings are listed,
  * with the passage each one rests on, in the design notes at the repository
  * root.  Parts of this file that no external fact pins carry the marker
  * "parity unpinned" below: the move order (R5), the per-cell halving on
@@ -21,6 +21,7 @@
  * Style: straight loops over row-major cells, one environment at a time, no
  * bit tricks, no precomputed tables.
  */
+#include <math.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -582,6 +583,201 @@ int orc_run(const orc_cfg *cfg, int32_t E, orc_batch *b, uint64_t seed_act, uint
         if (orc_sample_batch(cfg, E, b, seed_act, step0 + (uint64_t)t, actions) != 0) return -1;
         if (orc_step_batch(cfg, E, b, actions, rewards, done) != 0) return -1;
         if (orc_observe_batch(cfg, E, b, obs) != 0) return -1;
+    }
+    return 0;
+}
+
+/* ======================================================================
+ * The paper's full feature tensor (Appendix A, table of observation
+ * channels; reading R17): C = 24 + 2 * 7 = 38 float32 maps per player.
+ *
+ * Per env the oracle keeps, for the current episode, a running memory of
+ * what each player has seen (the persistent channels 4..8, 20, 21) and the
+ * own- and enemy-army channel values of the last 8 recorded frames (for the
+ * delta stacks 24..37).  A frame is the state after a step, keyed by its
+ * turn; recording the same turn twice changes nothing, and a turn with no
+ * recorded frame (before the episode, or skipped by the caller) counts as
+ * an empty board.  A state of another episode starts a fresh memory.
+ * parity unpinned for the readings themselves (R17): the channel
+ * definitions below are how this implementation reads the table.
+ * ==================================================================== */
+#define ORC_FEAT_C 38
+#define ORC_HIST 7           /* H_hist, the delta stack depth */
+#define ORC_FRAMES 8         /* frames t-7 .. t */
+
+typedef struct orc_fmem {
+    int32_t valid;                                /* 0: no frame recorded yet */
+    uint32_t episode;
+    uint8_t seen[ORC_MAX_P][ORC_MAX_CELLS];       /* ever visible */
+    uint8_t enemy_seen[ORC_MAX_P][ORC_MAX_CELLS]; /* ever visible while enemy-owned */
+    uint8_t gen_seen[ORC_MAX_P][ORC_MAX_CELLS];   /* ever visible as a general */
+    uint8_t castle_seen[ORC_MAX_P][ORC_MAX_CELLS];
+    uint8_t mtn_seen[ORC_MAX_P][ORC_MAX_CELLS];
+    int32_t last_army[ORC_MAX_P][ORC_MAX_CELLS];  /* enemy army at the last visible frame (0 if none) */
+    int32_t last_enemy_turn[ORC_MAX_P][ORC_MAX_CELLS]; /* turn of the last enemy sighting, if enemy_seen */
+    int32_t n_frames;                             /* kept frames, oldest first */
+    int32_t frame_turn[ORC_FRAMES];
+    int32_t own[ORC_FRAMES][ORC_MAX_P][ORC_MAX_CELLS];   /* channel 1 of that frame */
+    int32_t enemy[ORC_FRAMES][ORC_MAX_P][ORC_MAX_CELLS]; /* channel 2 of that frame */
+} orc_fmem;
+
+/* An enemy of player p owns the cell: owned, and not by p's team. */
+static int enemy_of(const orc_env *s, int owner, int p)
+{
+    return owner >= 0 && !in_team(s, owner, p);
+}
+
+/* Team vision (Section IV-B, R10): a cell is visible to p if a cell of p's
+ * team lies in its 3 x 3 neighbourhood. */
+static int visible(const orc_env *s, int p, int cell)
+{
+    const int H = s->H, W = s->W, r = cell / W, c = cell % W;
+    for (int dr = -1; dr <= 1; dr++) {
+        for (int dc = -1; dc <= 1; dc++) {
+            int nr = r + dr, nc = c + dc;
+            if (nr < 0 || nr >= H || nc < 0 || nc >= W) continue;
+            if (in_team(s, s->owner[nr * W + nc], p)) return 1;
+        }
+    }
+    return 0;
+}
+
+/* Index of the kept frame with turn t (the latest such), or -1. */
+static int frame_at(const orc_fmem *m, int64_t t)
+{
+    for (int i = m->n_frames - 1; i >= 0; i--)
+        if (m->frame_turn[i] == t) return i;
+    return -1;
+}
+
+/* Record the current frame into the memory and write the 38 channels of
+ * every player: feat [P][38][H*W]. */
+static void features_env(const orc_env *s, orc_fmem *m, float *feat)
+{
+    const int H = s->H, W = s->W, HW = H * W, P = s->P;
+    int vis[ORC_MAX_P][ORC_MAX_CELLS];
+    int32_t land[ORC_MAX_P];
+    int64_t army[ORC_MAX_P];
+
+    if (!m->valid || m->episode != s->episode) {
+        memset(m, 0, sizeof(*m));
+        m->valid = 1;
+        m->episode = s->episode;
+    }
+    for (int p = 0; p < P; p++) {
+        land[p] = 0;
+        army[p] = 0;
+        for (int c = 0; c < HW; c++) vis[p][c] = visible(s, p, c);
+    }
+    for (int c = 0; c < HW; c++) {
+        if (s->owner[c] >= 0) {
+            land[s->owner[c]] += 1;
+            army[s->owner[c]] += s->army[c];
+        }
+    }
+
+    /* the running memory takes this frame first: "ever seen" includes now */
+    for (int p = 0; p < P; p++) {
+        for (int c = 0; c < HW; c++) {
+            if (!vis[p][c]) continue;
+            const int en = enemy_of(s, s->owner[c], p);
+            m->seen[p][c] = 1;
+            if (en) {
+                m->enemy_seen[p][c] = 1;
+                m->last_enemy_turn[p][c] = s->turn;
+            }
+            if (s->type[c] == T_GENERAL) m->gen_seen[p][c] = 1;
+            if (s->type[c] == T_CASTLE) m->castle_seen[p][c] = 1;
+            if (s->type[c] == T_MOUNTAIN) m->mtn_seen[p][c] = 1;
+            m->last_army[p][c] = en ? s->army[c] : 0;
+        }
+    }
+
+    /* keep the frame (a repeated turn replaces its own entry) */
+    int slot;
+    if (m->n_frames > 0 && m->frame_turn[m->n_frames - 1] == s->turn) {
+        slot = m->n_frames - 1;
+    } else {
+        if (m->n_frames == ORC_FRAMES) {
+            memmove(&m->frame_turn[0], &m->frame_turn[1], sizeof(int32_t) * (ORC_FRAMES - 1));
+            memmove(&m->own[0], &m->own[1], sizeof(m->own[0]) * (ORC_FRAMES - 1));
+            memmove(&m->enemy[0], &m->enemy[1], sizeof(m->enemy[0]) * (ORC_FRAMES - 1));
+            m->n_frames--;
+        }
+        slot = m->n_frames++;
+    }
+    m->frame_turn[slot] = s->turn;
+    for (int p = 0; p < P; p++) {
+        for (int c = 0; c < HW; c++) {
+            m->own[slot][p][c] = s->owner[c] == p ? s->army[c] : 0;
+            m->enemy[slot][p][c] = (vis[p][c] && enemy_of(s, s->owner[c], p)) ? s->army[c] : 0;
+        }
+    }
+
+    for (int p = 0; p < P; p++) {
+        int32_t opp_land = 0;
+        int64_t opp_army = 0;
+        for (int q = 0; q < P; q++) {
+            if (q != p && !in_team(s, q, p)) {
+                opp_land += land[q];
+                opp_army += army[q];
+            }
+        }
+        float *f = feat + (size_t)p * ORC_FEAT_C * HW;
+        for (int c = 0; c < HW; c++) {
+            const int r = c / W, col = c % W;
+            const int o = s->owner[c], t = s->type[c], v = vis[p][c];
+            const int32_t a = s->army[c];
+            const int en = enemy_of(s, o, p);
+            f[0 * HW + c] = (float)(v ? a : 0);
+            f[1 * HW + c] = (float)(o == p ? a : 0);
+            f[2 * HW + c] = (float)(v && en ? a : 0);
+            f[3 * HW + c] = (float)(v && o < 0 ? a : 0);
+            f[4 * HW + c] = (float)m->seen[p][c];
+            f[5 * HW + c] = (float)m->enemy_seen[p][c];
+            f[6 * HW + c] = (float)m->gen_seen[p][c];
+            f[7 * HW + c] = (float)m->castle_seen[p][c];
+            f[8 * HW + c] = (float)m->mtn_seen[p][c];
+            f[9 * HW + c] = (float)(v && o < 0 && t != T_MOUNTAIN);
+            f[10 * HW + c] = (float)(o == p);
+            f[11 * HW + c] = (float)(v && en);
+            f[12 * HW + c] = (float)(!v);
+            f[13 * HW + c] = (float)(!v && (t == T_MOUNTAIN || t == T_CASTLE || m->gen_seen[p][c]));
+            f[14 * HW + c] = (float)s->turn;
+            f[15 * HW + c] = (float)((double)(s->turn % 50) / 50.0);
+            f[16 * HW + c] = (float)land[p];
+            f[17 * HW + c] = (float)army[p];
+            f[18 * HW + c] = (float)opp_land;
+            f[19 * HW + c] = (float)opp_army;
+            f[20 * HW + c] = (float)m->last_army[p][c];
+            f[21 * HW + c] = (v || !m->enemy_seen[p][c])
+                                 ? 0.0f
+                                 : (float)(log1p((double)(s->turn - m->last_enemy_turn[p][c])) / 5.0);
+            f[22 * HW + c] = (float)((double)col / (double)(W - 1));
+            f[23 * HW + c] = (float)((double)r / (double)(H - 1));
+            for (int k = 0; k < ORC_HIST; k++) {
+                const int i0 = frame_at(m, (int64_t)s->turn - k), i1 = frame_at(m, (int64_t)s->turn - k - 1);
+                const int64_t own0 = i0 >= 0 ? m->own[i0][p][c] : 0, own1 = i1 >= 0 ? m->own[i1][p][c] : 0;
+                const int64_t en0 = i0 >= 0 ? m->enemy[i0][p][c] : 0, en1 = i1 >= 0 ? m->enemy[i1][p][c] : 0;
+                f[(24 + k) * HW + c] = (float)(own0 - own1);
+                f[(24 + ORC_HIST + k) * HW + c] = (float)(en0 - en1);
+            }
+        }
+    }
+}
+
+/* Size of one env's feature memory; the caller zero-fills E of them once. */
+int64_t orc_fmem_bytes(void) { return (int64_t)sizeof(orc_fmem); }
+
+/* Features of every env: mem [E] orc_fmem (updated), feat [E][P][38][H*W]. */
+int orc_features_batch(const orc_cfg *cfg, int32_t E, const orc_batch *b, void *mem, float *feat)
+{
+    orc_env s;
+    if (!cfg_ok(cfg)) return -1;
+    const size_t per = (size_t)cfg->P * ORC_FEAT_C * cfg->H * cfg->W;
+    for (int e = 0; e < E; e++) {
+        load_env(&s, cfg, b, e);
+        features_env(&s, (orc_fmem *)mem + e, feat + (size_t)e * per);
     }
     return 0;
 }
