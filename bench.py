@@ -116,6 +116,42 @@ def run_step_alone(b, wl, torch, stream, steps: int, first_step: int) -> dict:
             "achieved_gbs": alone * b.n_envs / (float(ms.mean()) / 1e3) / 1e9, "algorithmic_bytes_per_frame": alone}
 
 
+def feature_bytes(wl) -> dict:
+    """Algorithmic HBM bytes per frame of gen_features: it reads the state,
+    the memory header, the per-player memory (1 + 4 + 4 bytes per cell) and
+    the 7 earlier frames of the ring (6 bytes per cell each); it writes the
+    per-player memory, this frame's ring slot, the header and the float32
+    [P][38][H][W] features."""
+    HW, P = wl.H * wl.W, wl.P
+    read = HW * 6 + 32 + 64 + 9 * P * HW + 7 * 6 * HW
+    write = 9 * P * HW + 6 * HW + 40 + 38 * 4 * P * HW
+    return {"read": read, "write": write, "total": read + write}
+
+
+def run_features(b, wl, torch, stream, steps: int, first_step: int) -> dict:
+    """The 38-channel features (gen_features) after every fused step; only
+    the features launch lies between the events."""
+    b.features()                                  # allocates the memory and the output
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for t in range(steps):
+        b.step_sample(wl.actor_seed, first_step + t)
+        ev0[t].record(stream)
+        b.features()
+        ev1[t].record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev0[t].elapsed_time(ev1[t]) for t in range(steps)])
+    by = feature_bytes(wl)
+    out = {"kernel": "k_features (gen_features)", "steps": steps, "kernel_ms_mean": float(ms.mean()),
+           "kernel_ms_p50": float(np.percentile(ms, 50)), "frames_per_s": b.n_envs / (float(ms.mean()) / 1e3),
+           "algorithmic_bytes_per_frame": by["total"],
+           "achieved_gbs": by["total"] * b.n_envs / (float(ms.mean()) / 1e3) / 1e9}
+    out["frac_of_peak"] = out["achieved_gbs"] / HBM_PEAK_GBS
+    b.feat = b.fmem = None
+    torch.cuda.empty_cache()
+    return out
+
+
 def pool_bytes_per_frame(specs) -> float:
     """Mean algorithmic bytes per frame of the pooled step (same accounting as
     step_bytes, per env shape; the scalar record also carries the step
@@ -351,6 +387,7 @@ def main() -> int:
     }
     if not args.no_extras:
         out["step_alone"] = run_step_alone(b, wl, torch, stream, min(K, 1000), W + K + 1)
+        out["features"] = run_features(b, wl, torch, stream, 100, W + K + min(K, 1000) + 1)
         del b
         torch.cuda.empty_cache()
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(torch)

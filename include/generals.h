@@ -189,6 +189,46 @@ int gen_step_sample(const gen_state *st, int32_t *d_actions, uint64_t actor_seed
 /* Observation of the current state (no state change). */
 int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The paper's full feature tensor (Appendix A, table of observation
+ * channels): float32 [E][P][38][H][W] per call, for every player of every
+ * env, from the current state and a per-env memory that the calls keep.
+ *   0 army on visible cells          1 army on the player's own cells
+ *   2 army on visible enemy cells    3 army on visible neutral cells
+ *   4 ever visible                   5 ever seen enemy-owned
+ *   6 general ever seen              7 castle ever seen
+ *   8 mountain ever seen             9 visible neutral non-mountain
+ *  10 own cell                      11 visible enemy cell
+ *  12 fog                           13 fog over a mountain, castle or a general seen before
+ *  14 turn                          15 (turn mod 50) / 50
+ *  16 own land                      17 own army total
+ *  18 land of all enemies           19 army of all enemies
+ *  20 enemy army at the cell's last visible frame
+ *  21 log(1 + turns since an enemy was last seen there) / 5 (0 while visible)
+ *  22 col / (W - 1)                 23 row / (H - 1)
+ *  24+k, 31+k (k = 0..6): own (channel 1), resp. visible-enemy (channel 2)
+ *     army of the frame of turn t-k minus that of turn t-k-1.
+ * "Enemy" = owned by a player outside the observer's team; vision is the
+ * team's (as in gen_step).  A frame is the state after a step, keyed by its
+ * turn: call gen_features once after gen_reset and after every step.  A turn
+ * that was not recorded counts as an empty board in the delta stacks; the
+ * first call on a state of a new episode (auto-reset) starts a fresh memory;
+ * calling twice on the same state returns the same tensor.  Values are
+ * exact integers converted to float32 (round to nearest even), except 15,
+ * 21, 22 and 23 (computed in double, rounded once to float32).
+ * ---------------------------------------------------------------------- */
+#define GEN_FEAT_CHANNELS 38
+#define GEN_FEAT_HISTORY 7
+
+/* Device bytes of the feature memory of the batch `st` (0 if st is invalid).
+ * The caller allocates it (256-byte aligned) and zero-fills it once before
+ * the first gen_features call; after that only gen_features writes it. */
+uint64_t gen_feat_mem_bytes(const gen_state *st);
+
+/* Record the current state of every env into d_mem and write the features
+ * d_feat float32 [E][P][38][H][W].  GEN_ENOMEM if mem_bytes is too small. */
+int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, void *stream);
+
 /* Blocking copies between the device buffer and the public host format
  * (synchronises `stream`).  gen_set_state rejects (GEN_EINVAL) contents the
  * kernels cannot take: owner outside [-1, P), type outside [0, 3], negative

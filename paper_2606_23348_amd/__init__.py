@@ -111,6 +111,8 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_sample_actions.argtypes = [P(gen_state), u64, u64, vp, vp]
     L.gen_step_sample.argtypes = [P(gen_state), vp, u64, u64, vp, vp, vp, vp, vp, vp]
     L.gen_observe.argtypes = [P(gen_state), vp, vp]
+    L.gen_feat_mem_bytes.argtypes, L.gen_feat_mem_bytes.restype = [P(gen_state)], u64
+    L.gen_features.argtypes = [P(gen_state), vp, u64, vp, vp]
     L.gen_get_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_set_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_get_envs.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
@@ -136,7 +138,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_server_drive.argtypes = [vp, i32, i32, vp, vp, P(gen_params), u64, u64, vp, i32, ctypes.c_int64, i32,
                                    P(gen_server_stats)]
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
-              "gen_observe", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
+              "gen_observe", "gen_features", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
               "gen_pool_get_env", "gen_server_create", "gen_server_destroy", "gen_server_open",
@@ -253,6 +255,21 @@ def _host_struct(h: dict) -> gen_host_state:
     return gen_host_state(*(h[k].ctypes.data for k in _HOST_TYPES))
 
 
+FEAT_CHANNELS = 38
+
+
+def gen_feat_mem_bytes(st: gen_state) -> int:
+    n = int(lib().gen_feat_mem_bytes(ctypes.byref(st)))
+    if n == 0:
+        raise GenError(GEN_EINVAL, gen_last_error())
+    return n
+
+
+def gen_features(st: gen_state, mem, feat, stream=None):
+    _check(lib().gen_features(ctypes.byref(st), _ptr(mem), mem.numel() * mem.element_size(), _ptr(feat),
+                              _stream(stream)))
+
+
 def gen_get_state(st: gen_state, stream=None) -> dict:
     """Blocking copy of the device state into the public host format (numpy)."""
     h = _host_arrays(st.n_envs, st.H * st.W, st.n_players)
@@ -294,6 +311,7 @@ class Batch:
         self.dones = torch.zeros(n_envs, dtype=torch.uint8, device=device)
         self.land = torch.zeros((n_envs, P), dtype=torch.int32, device=device) if scoreboard else None
         self.army = torch.zeros((n_envs, P), dtype=torch.int64, device=device) if scoreboard else None
+        self.feat = self.fmem = None           # 38-channel features, allocated by features()
         self.st = gen_reset(seed, env_base, n_envs, H, W, mode, params, self.buf, self.obs, stream)
 
     def sample(self, actor_seed: int, step_idx: int, stream=None):
@@ -308,6 +326,18 @@ class Batch:
 
     def observe(self, stream=None):
         gen_observe(self.st, self.obs, stream)
+
+    def features(self, stream=None):
+        """The 38-channel features float32 [E][P][38][H][W] of the current
+        state into self.feat (allocated, with its zero-filled memory, on the
+        first call).  Call once after reset and after every step."""
+        if getattr(self, "feat", None) is None:
+            import torch
+            dev = self.buf.device
+            self.fmem = torch.zeros(gen_feat_mem_bytes(self.st), dtype=torch.uint8, device=dev)
+            self.feat = torch.zeros((self.n_envs, self.P, FEAT_CHANNELS, self.H, self.W), dtype=torch.float32,
+                                    device=dev)
+        gen_features(self.st, self.fmem, self.feat, stream)
 
     def get_state(self, stream=None) -> dict:
         return gen_get_state(self.st, stream)

@@ -352,6 +352,38 @@ int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream)
     return ok();
 }
 
+uint64_t gen_feat_mem_bytes(const gen_state *st)
+{
+    if (check_state(st) != GEN_OK) return 0;
+    return (uint64_t)gen::feat_block(st->stride, st->n_players).bytes * (uint64_t)st->n_envs;
+}
+
+int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (d_mem == nullptr || !aligned(d_mem, 256))
+        return fail(GEN_EINVAL, "d_mem must be a 256-byte aligned device pointer");
+    if (d_feat == nullptr || !aligned(d_feat, 4)) return fail(GEN_EINVAL, "d_feat must be a 4-byte aligned device pointer");
+    const gen::FeatBlock fb = gen::feat_block(st->stride, st->n_players);
+    const uint64_t need = (uint64_t)fb.bytes * (uint64_t)st->n_envs;
+    if (mem_bytes < need)
+        return fail(GEN_ENOMEM, "feature memory holds %llu bytes, the batch needs %llu", (unsigned long long)mem_bytes,
+                    (unsigned long long)need);
+    const gen::EnvArgs ea = env_args(*st);
+    gen::FeatArgs a{};
+    a.g = ea.g;
+    a.blk = fb;
+    a.sc = ea.sc;
+    a.owner = ea.owner;
+    a.type = ea.type;
+    a.army = ea.army;
+    a.mem = static_cast<uint8_t *>(d_mem);
+    a.feat = d_feat;
+    hipError_t e = gen::launch_features(a, st->n_envs, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "features launch");
+    return ok();
+}
+
 int gen_get_state(const gen_state *st, gen_host_state *h, void *stream)
 {
     if (check_state(st) != GEN_OK) return GEN_EINVAL;

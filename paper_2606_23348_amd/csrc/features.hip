@@ -1,0 +1,250 @@
+// features.hip -- the paper's full feature tensor (Appendix A, table of
+// observation channels; reading R17 of this library): 38 float32 maps per
+// player and env, computed by one wave64 per env from the env's state and a
+// per-env memory in HBM (persistent masks, the last enemy sighting per cell,
+// a ring of the last 8 frames).
+//
+// Memory traffic dominates (the output alone is 152 bytes per cell and
+// player), so the kernel keeps every store coalesced: lane i of a round
+// handles cell 64r + i, and each of the 38 channel stores of a player is one
+// contiguous 256-byte wave store, nontemporal.  The state sits in LDS only
+// for the ballots and the team-vision dilation.  The delta stacks walk the
+// ring one frame at a time for all players, so only two running values per
+// player stay live.
+#include "internal.hpp"
+
+namespace gen {
+
+namespace {
+
+constexpr int kFeatC = 38;
+constexpr int kHist = 7;
+
+enum : uint32_t { B_SEEN = 1, B_ENEMY = 2, B_GENERAL = 4, B_CASTLE = 8, B_MOUNTAIN = 16 };
+
+// Owned by a player outside p's team (team = p, and p ^ 2 in 2v2).
+__device__ __forceinline__ bool enemy_of(int owner, int p, int mode)
+{
+    return owner >= 0 && owner != p && !(mode == MODE_2V2 && owner == (p ^ 2));
+}
+
+// Every per-env access goes through a raw buffer descriptor of the env's own
+// block (base in scalar registers, bounds = the block), so a channel or
+// memory-section offset is a scalar operand rather than a 64-bit address
+// per lane, and an access past the block is dropped by the hardware.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRawWord3 = 0x00020000;      // gfx9-family raw (stride 0) buffer descriptor flags
+constexpr int kNT = 2;                     // cache policy of the stores: nontemporal
+
+__device__ __forceinline__ Rsrc rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawWord3);
+}
+
+__device__ __forceinline__ float age_of(int32_t dt)
+{
+    return (float)(log1p((double)dt) / 5.0);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_features(FeatArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int e = blockIdx.x, lane = lane_id();
+    const Geom g = a.g;
+    const FeatBlock fb = a.blk;
+    const int S = g.S, HW = g.HW, P = g.P;
+
+    // LDS: owner [S] | type [S] | army int32 [S] | obm [P][16] | vis [P][16]
+    int8_t *Lo = reinterpret_cast<int8_t *>(smem);
+    uint8_t *Lt = smem + S;
+    int32_t *La = reinterpret_cast<int32_t *>(smem + 2 * S);
+    uint64_t *obm = reinterpret_cast<uint64_t *>(smem + 6 * S);
+    uint64_t *vis = obm + P * 16;
+
+    const EnvScalars s = a.sc[e];
+    {
+        const size_t cell0 = (size_t)e * S;
+        const uint4 *go = reinterpret_cast<const uint4 *>(a.owner + cell0);
+        const uint4 *gt = reinterpret_cast<const uint4 *>(a.type + cell0);
+        const uint4 *ga = reinterpret_cast<const uint4 *>(a.army + cell0);
+        const int n16 = S >> 4;
+        for (int i = lane; i < n16; i += kWave) {
+            reinterpret_cast<uint4 *>(Lo)[i] = go[i];
+            reinterpret_cast<uint4 *>(Lt)[i] = gt[i];
+        }
+        for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(La)[i] = ga[i];
+    }
+    wave_sync();
+
+    // owned-cell bitmaps, team vision, land and army totals
+    int land[kMaxP];
+    int64_t armt[kMaxP];
+#pragma unroll
+    for (int p = 0; p < kMaxP; ++p) { land[p] = 0; armt[p] = 0; }
+    for (int w = 0; w < g.NW; ++w) {
+        const int c = w * 64 + lane;
+        const int o = c < HW ? (int)Lo[c] : -1;
+        for (int p = 0; p < P; ++p) {
+            const uint64_t m = ballot(o == p);
+            if (lane == 0) obm[p * 16 + w] = m;
+        }
+        if (o >= 0) {
+            const int32_t av = La[c];
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p)
+                if (o == p) { land[p] += 1; armt[p] += av; }
+        }
+    }
+    wave_sync();
+    team_vision(obm, vis, g);
+#pragma unroll
+    for (int p = 0; p < kMaxP; ++p) {
+        if (p < P) {               // wave-uniform totals live in scalar registers
+            land[p] = readfirst((int)wave_sum_u32((uint32_t)land[p]));
+            const uint64_t at = (uint64_t)wave_sum_i64(armt[p]);
+            armt[p] = (int64_t)(((uint64_t)(uint32_t)readfirst((int)(at >> 32)) << 32) |
+                                (uint32_t)readfirst((int)(uint32_t)at));
+        }
+    }
+    wave_sync();
+
+    // memory header: a block of another episode (or never used) starts empty
+    uint8_t *blk = a.mem + (size_t)e * fb.bytes;
+    uint32_t *hdr = reinterpret_cast<uint32_t *>(blk);
+    const int32_t t = s.turn;
+    const int slot = t & 7;
+    const bool fresh = readfirst((int)hdr[0]) != (int)kFeatMagic || (uint32_t)readfirst((int)hdr[1]) != s.episode;
+    int32_t stamp[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) stamp[j] = fresh ? -1 : readfirst((int)hdr[2 + j]);
+    uint32_t hv = 0;                  // bit k: the frame of turn t - k is in the ring
+#pragma unroll
+    for (int k = 1; k <= kHist; ++k) {
+        const int32_t tau = t - k;
+        if (tau >= 0 && stamp[tau & 7] == tau) hv |= 1u << k;
+    }
+
+    const float ch15 = (float)((double)(t % 50) / 50.0);
+    float *fe = a.feat + (size_t)e * (size_t)P * kFeatC * HW;
+
+    const Rsrc rm = rsrc(blk, fb.bytes);
+    const Rsrc rf = rsrc(fe, (uint32_t)(P * kFeatC * HW * 4));
+    for (int c = lane; c < HW; c += kWave) {
+        const int o = Lo[c], ty = Lt[c];
+        const int32_t av = La[c];
+        const int w = c >> 6, b = c & 63;
+        uint32_t vb = 0;
+        for (int p = 0; p < P; ++p) vb |= (uint32_t)((vis[p * 16 + w] >> b) & 1ull) << p;
+
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)o, rm, c, (int)fb.fowner + slot * S, kNT);
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)vb, rm, c, (int)fb.fvis + slot * S, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)av, rm, 4 * c, (int)fb.farmy + 4 * slot * S, kNT);
+
+        const int row = div_w(c, g), col = c - row * g.W;
+        const float cx = (float)((double)col / (double)(g.W - 1));
+        const float cy = (float)((double)row / (double)(g.H - 1));
+
+        int32_t own_prev[kMaxP], en_prev[kMaxP];
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p) {
+            if (p >= P) break;
+            const bool v = (vb >> p) & 1u;
+            const bool en = enemy_of(o, p, g.mode);
+            uint32_t bits = fresh ? 0u : (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.bits + p * S, 0);
+            int32_t last = fresh ? 0 : (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * c, (int)fb.last + 4 * p * S, 0);
+            int32_t lturn = fresh ? 0 : (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * c, (int)fb.lturn + 4 * p * S, 0);
+            if (v) {
+                bits |= B_SEEN;
+                if (en) { bits |= B_ENEMY; lturn = t; }
+                if (ty == GENERAL) bits |= B_GENERAL;
+                if (ty == CASTLE) bits |= B_CASTLE;
+                if (ty == MOUNTAIN) bits |= B_MOUNTAIN;
+                last = en ? av : 0;
+            }
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)bits, rm, c, (int)fb.bits + p * S, kNT);
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)last, rm, 4 * c, (int)fb.last + 4 * p * S, kNT);
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)lturn, rm, 4 * c, (int)fb.lturn + 4 * p * S, kNT);
+
+            int32_t opp_land = 0;
+            int64_t opp_army = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxP; ++q) {
+                if (q < P && q != p && !(g.mode == MODE_2V2 && q == (p ^ 2))) {
+                    opp_land += land[q];
+                    opp_army += armt[q];
+                }
+            }
+            const int pb = p * kFeatC * HW * 4;
+            auto put = [&](int ch, float x) {
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rf, 4 * c, pb + ch * HW * 4, kNT);
+            };
+            put(0, (float)(v ? av : 0));
+            put(1, (float)(o == p ? av : 0));
+            put(2, (float)(v && en ? av : 0));
+            put(3, (float)(v && o < 0 ? av : 0));
+            put(4, (float)(bits & 1u));
+            put(5, (float)((bits >> 1) & 1u));
+            put(6, (float)((bits >> 2) & 1u));
+            put(7, (float)((bits >> 3) & 1u));
+            put(8, (float)((bits >> 4) & 1u));
+            put(9, (v && o < 0 && ty != MOUNTAIN) ? 1.0f : 0.0f);
+            put(10, o == p ? 1.0f : 0.0f);
+            put(11, (v && en) ? 1.0f : 0.0f);
+            put(12, v ? 0.0f : 1.0f);
+            put(13, (!v && (ty == MOUNTAIN || ty == CASTLE || (bits & B_GENERAL))) ? 1.0f : 0.0f);
+            put(14, (float)t);
+            put(15, ch15);
+            put(16, (float)land[p]);
+            put(17, (float)armt[p]);
+            put(18, (float)opp_land);
+            put(19, (float)opp_army);
+            put(20, (float)last);
+            put(21, (v || !(bits & B_ENEMY)) ? 0.0f : age_of(t - lturn));
+            put(22, cx);
+            put(23, cy);
+            own_prev[p] = o == p ? av : 0;
+            en_prev[p] = (v && en) ? av : 0;
+        }
+
+        // delta stacks: frame t-k-1 from the ring (absent: empty board)
+#pragma unroll 1
+        for (int k = 0; k < kHist; ++k) {
+            const int sl = (t - k - 1) & 7;
+            const bool have = (hv >> (k + 1)) & 1u;
+            const int q = have ? (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fowner + sl * S, 0) : -1;
+            const uint32_t qv = have ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fvis + sl * S, 0) : 0u;
+            const int32_t qa = have ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * c, (int)fb.farmy + 4 * sl * S, 0) : 0;
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p) {
+                if (p >= P) break;
+                const int pb = p * kFeatC * HW * 4;
+                const int32_t own_k = q == p ? qa : 0;
+                const int32_t en_k = (((qv >> p) & 1u) && enemy_of(q, p, g.mode)) ? qa : 0;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)(own_prev[p] - own_k)), rf, 4 * c,
+                                                      pb + (24 + k) * HW * 4, kNT);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)(en_prev[p] - en_k)), rf, 4 * c,
+                                                      pb + (24 + kHist + k) * HW * 4, kNT);
+                own_prev[p] = own_k;
+                en_prev[p] = en_k;
+            }
+        }
+    }
+
+    if (lane == 0) {
+        hdr[0] = kFeatMagic;
+        hdr[1] = s.episode;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) hdr[2 + j] = (uint32_t)(j == slot ? t : stamp[j]);
+    }
+}
+
+hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)
+{
+    const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace gen

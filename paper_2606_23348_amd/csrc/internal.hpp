@@ -67,6 +67,48 @@ struct ServeReq {
     uint32_t n_envs, actor, wg_begin, pad;
 };
 
+// One env's block of the feature memory (38-channel features), byte offsets:
+//   header  64 B  {uint32 magic; uint32 episode; int32 stamp[8]; pad}
+//           stamp[j] = turn of the frame held in ring slot j (-1: none)
+//   bits    uint8 [P][S]   bit 0 seen, 1 enemy seen, 2 general seen,
+//                          3 castle seen, 4 mountain seen
+//   last    int32 [P][S]   enemy army at the cell's last visible frame
+//   lturn   int32 [P][S]   turn of the last enemy sighting (valid with bit 1)
+//   fowner  int8  [8][S]   ring of the last 8 frames, slot = turn mod 8:
+//   fvis    uint8 [8][S]     owner, visibility (bit p: visible to p), army
+//   farmy   int32 [8][S]
+struct FeatBlock {
+    uint32_t bits, last, lturn, fowner, fvis, farmy, bytes;
+};
+
+__host__ __device__ inline FeatBlock feat_block(int S, int P)
+{
+    FeatBlock b;
+    b.bits = 64;
+    b.last = b.bits + (uint32_t)(P * S);
+    b.lturn = b.last + (uint32_t)(4 * P * S);
+    b.fowner = b.lturn + (uint32_t)(4 * P * S);
+    b.fvis = b.fowner + (uint32_t)(8 * S);
+    b.farmy = b.fvis + (uint32_t)(8 * S);
+    b.bytes = (b.farmy + (uint32_t)(32 * S) + 255u) & ~255u;
+    return b;
+}
+
+constexpr uint32_t kFeatMagic = 0x3846454Eu;   // header tag of a block in use
+
+struct FeatArgs {
+    Geom g;
+    FeatBlock blk;
+    const EnvScalars *sc;
+    const int8_t *owner;
+    const uint8_t *type;
+    const int32_t *army;
+    uint8_t *mem;
+    float *feat;
+};
+
+hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream);
+
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);
 hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,

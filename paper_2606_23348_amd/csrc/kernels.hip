@@ -380,6 +380,24 @@ __device__ __forceinline__ uint32_t vismask(uint32_t code4)
     return (((code4 >> 6) & 0x01010101u) ^ 0x01010101u) * 0xFFu;
 }
 
+// Code bytes of the four cells of quad q for player p (bit k = obs channel k,
+// k < 7; reading R16): SWAR over the owner and type bytes and 4 vision bits.
+__device__ __forceinline__ uint32_t code_quad(const Lds &L, const Geom &g, int p, uint32_t ally, int q)
+{
+    const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
+    const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
+    const uint32_t vb = (uint32_t)(L.vis[p * 16 + (q >> 4)] >> ((q & 15) * 4)) & 0xFu;
+    const uint32_t visb = spread4(vb);
+    const uint32_t eqp = bytes_eq(o4, (uint32_t)p), eqa = bytes_eq(o4, ally);
+    const uint32_t neutral = (o4 >> 7) & 0x01010101u;
+    const uint32_t enemy = (neutral ^ 0x01010101u) & ~eqp & ~eqa;
+    const uint32_t mtn = t4 & ~(t4 >> 1) & 0x01010101u;
+    const uint32_t cas = (t4 >> 1) & ~t4 & 0x01010101u;
+    const uint32_t gen = t4 & (t4 >> 1) & 0x01010101u;
+    return eqp | ((enemy & visb) << 1) | ((neutral & ~mtn & visb) << 2) | ((mtn & visb) << 3) | ((cas & visb) << 4) |
+           ((gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
+}
+
 // One obs byte (slow path for dwords that straddle two planes).
 __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32_t b)
 {
@@ -572,9 +590,10 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
                 }
             }
             if (KIND != K_OBSERVE) {
-                ga[q] = make_int4(av[0], av[1], av[2], av[3]);
-                go[q] = o4;
-                if (write_type) gt[q] = t4;
+                st_nt(reinterpret_cast<uint4 *>(ga + q),
+                      make_uint4((uint32_t)av[0], (uint32_t)av[1], (uint32_t)av[2], (uint32_t)av[3]));
+                st_nt(go + q, o4);
+                if (write_type) st_nt(gt + q, t4);
             }
             uint32_t ac = 0;
 #pragma unroll
@@ -615,55 +634,45 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     }
     wave_sync();
 
-    // ---- fog (Section IV-B): 8-neighbour dilation = horizontal 3 then vertical 3
-    {
-        const int ppr = kWave / g.NW;                 // players per round
-        const int lp = lane / g.NW, w = lane - lp * g.NW;
-        const ColMasks cm = col_masks(w, g);
-        for (int p0 = 0; p0 < g.P; p0 += ppr) {
-            const int p = p0 + lp;
-            const bool valid = lp < ppr && p < g.P;
-            uint64_t m = valid ? L.obm[p * 16 + w] : 0ull;
-            if (valid && g.mode == MODE_2V2) m |= L.obm[(p ^ 2) * 16 + w];   // team vision (R10)
-            uint64_t mp = shfl64(m, lane - 1), mn = shfl64(m, lane + 1);
-            if (w == 0) mp = 0ull;
-            if (w == g.NW - 1) mn = 0ull;
-            const uint64_t h = m | (((m << 1) | (mp >> 63)) & ~cm.col0) | (((m >> 1) | (mn << 63)) & ~cm.colL);
-            uint64_t hp = shfl64(h, lane - 1), hn = shfl64(h, lane + 1);
-            if (w == 0) hp = 0ull;
-            if (w == g.NW - 1) hn = 0ull;
-            const uint64_t v = (h | (h << g.W) | (hp >> (64 - g.W)) | (h >> g.W) | (hn << (64 - g.W))) & cm.valid;
-            if (valid) L.vis[p * 16 + w] = v;
-        }
-    }
+    // ---- fog (Section IV-B, team vision R10)
+    team_vision(L.obm, L.vis, g);
     wave_sync();
 
-    // ---- per-(player, cell) code byte: bit k = obs channel k for k < 7 (reading R16)
-    {
+    // Planes of a multiple of 4 cells: each lane takes 4 cells, computes their
+    // code bytes in registers and writes them straight into all 8 channel
+    // planes (4-byte stores, 256 contiguous bytes per wave store).  Other
+    // shapes stage the code bytes in LDS for the chunk writers below.
+    const bool quad_obs =
+        (OBSV == OBS_A16 || OBSV == OBS_A4) || (OBSV == OBS_RUNTIME && (g.HW & 3) == 0);
+    if (quad_obs) {
+        if (io.obs != nullptr) {
+            const int nq = g.HW >> 2;
+            for (int p = 0; p < g.P; ++p) {
+                const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
+                uint8_t *pb = io.obs + (size_t)p * 8 * g.HW;
+                for (int q = lane; q < nq; q += kWave) {
+                    const uint32_t code = code_quad(L, g, p, ally, q);
+                    const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[q];
+#pragma unroll
+                    for (int ch = 0; ch < 7; ++ch)
+                        st_nt(reinterpret_cast<uint32_t *>(pb + ch * g.HW) + q, (code >> ch) & 0x01010101u);
+                    st_nt(reinterpret_cast<uint32_t *>(pb + 7 * g.HW) + q, ac & vismask(code));
+                }
+            }
+        }
+    } else {
+        // ---- per-(player, cell) code bytes staged in LDS
         const int nq = (g.HW + 3) >> 2;
         for (int p = 0; p < g.P; ++p) {
             const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
             uint32_t *cw = reinterpret_cast<uint32_t *>(L.code + p * g.S);
-            for (int q = lane; q < nq; q += kWave) {
-                const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
-                const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
-                const uint32_t vb = (uint32_t)(L.vis[p * 16 + (q >> 4)] >> ((q & 15) * 4)) & 0xFu;
-                const uint32_t visb = spread4(vb);
-                const uint32_t eqp = bytes_eq(o4, (uint32_t)p), eqa = bytes_eq(o4, ally);
-                const uint32_t neutral = (o4 >> 7) & 0x01010101u;
-                const uint32_t enemy = (neutral ^ 0x01010101u) & ~eqp & ~eqa;
-                const uint32_t mtn = t4 & ~(t4 >> 1) & 0x01010101u;
-                const uint32_t cas = (t4 >> 1) & ~t4 & 0x01010101u;
-                const uint32_t gen = t4 & (t4 >> 1) & 0x01010101u;
-                cw[q] = eqp | ((enemy & visb) << 1) | ((neutral & ~mtn & visb) << 2) | ((mtn & visb) << 3) |
-                        ((cas & visb) << 4) | ((gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
-            }
+            for (int q = lane; q < nq; q += kWave) cw[q] = code_quad(L, g, p, ally, q);
         }
     }
     wave_sync();
 
-    // ---- observation stream: uint8 [P][8][H][W] per env, 16- or 8-byte stores
-    if (io.obs != nullptr) {
+    // ---- observation stream for the other plane sizes: 16- or 8-byte stores
+    if (io.obs != nullptr && !quad_obs) {
         const uint32_t B = (uint32_t)(g.P * 8 * g.HW);
         uint8_t *ob = io.obs;
         if (OBSV == OBS_RUNTIME) {
@@ -673,14 +682,14 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
                     const uint32_t b = k << 4;
                     uint32_t o[4];
                     obs_chunk<16, false>(L, g, b, o);
-                    *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
+                    st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
                 }
             } else {
                 for (uint32_t k = lane; k < (B >> 3); k += kWave) {
                     const uint32_t b = k << 3;
                     uint32_t o[2];
                     obs_chunk<8, false>(L, g, b, o);
-                    *reinterpret_cast<uint2 *>(ob + b) = make_uint2(o[0], o[1]);
+                    st_nt(reinterpret_cast<uint2 *>(ob + b), make_uint2(o[0], o[1]));
                 }
             }
         } else if (OBSV == OBS_A16) {
@@ -701,28 +710,28 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
                     out.z = ac.z & vismask(cd.z);
                     out.w = ac.w & vismask(cd.w);
                 }
-                *reinterpret_cast<uint4 *>(ob + b) = out;
+                st_nt(reinterpret_cast<uint4 *>(ob + b), out);
             }
         } else if (OBSV == OBS_A4) {
             for (uint32_t k = lane; k < (B >> 4); k += kWave) {
                 const uint32_t b = k << 4;
                 uint32_t o[4];
                 obs_chunk<16, true>(L, g, b, o);
-                *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
+                st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
             }
         } else if (OBSV == OBS_A1C16) {
             for (uint32_t k = lane; k < (B >> 4); k += kWave) {
                 const uint32_t b = k << 4;
                 uint32_t o[4];
                 obs_chunk<16, false>(L, g, b, o);
-                *reinterpret_cast<uint4 *>(ob + b) = make_uint4(o[0], o[1], o[2], o[3]);
+                st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
             }
         } else {
             for (uint32_t k = lane; k < (B >> 3); k += kWave) {
                 const uint32_t b = k << 3;
                 uint32_t o[2];
                 obs_chunk<8, false>(L, g, b, o);
-                *reinterpret_cast<uint2 *>(ob + b) = make_uint2(o[0], o[1]);
+                st_nt(reinterpret_cast<uint2 *>(ob + b), make_uint2(o[0], o[1]));
             }
         }
     }
