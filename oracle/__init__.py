@@ -78,7 +78,7 @@ def lib():
         _lib.orc_run.argtypes = [vp, i32, vp, u64, u64, i32, vp, vp, vp, vp]
         _lib.orc_fmem_bytes.argtypes = []
         _lib.orc_fmem_bytes.restype = ctypes.c_int64
-        _lib.orc_features_batch.argtypes = [vp, i32, vp, vp, vp]
+        _lib.orc_features_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         for f in ("orc_reset_batch", "orc_step_batch", "orc_observe_batch",
                   "orc_scoreboard_batch", "orc_sample_batch", "orc_run"):
             getattr(_lib, f).restype = ctypes.c_int
@@ -203,6 +203,7 @@ def run(cfg: Config, st: dict, seed_act: int, step0: int, n_steps: int):
 
 
 FEAT_CHANNELS = 38
+TOKEN_WINDOW = 512
 
 
 def feature_memory(E: int) -> np.ndarray:
@@ -211,15 +212,19 @@ def feature_memory(E: int) -> np.ndarray:
     return np.zeros((E, int(lib().orc_fmem_bytes())), np.uint8)
 
 
-def features(cfg: Config, st: dict, mem: np.ndarray) -> np.ndarray:
+def features(cfg: Config, st: dict, mem: np.ndarray, tokens: bool = False):
     """Record the current frame of every env into `mem` and return the
-    38-channel features float32 [E][P][38][H][W] (Appendix A, reading R17)."""
+    38-channel features float32 [E][P][38][H][W] (Appendix A, reading R17);
+    with tokens=True also the temporal tokens float32 [E][P][2][512]
+    (enemies' army total, then land, for the last 512 turns)."""
     E = st["turn"].shape[0]
     assert mem.shape[0] == E and mem.flags["C_CONTIGUOUS"]
     out = np.zeros((E, cfg.P, FEAT_CHANNELS, cfg.H, cfg.W), np.float32)
+    tok = np.zeros((E, cfg.P, 2, TOKEN_WINDOW), np.float32) if tokens else None
     c, b = cfg._c(), _batch(st)
-    _check(lib().orc_features_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(mem), _ptr(out)))
-    return out
+    _check(lib().orc_features_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(mem), _ptr(out),
+                                    _ptr(tok) if tokens else None))
+    return (out, tok) if tokens else out
 
 
 def philox(ctr, key) -> np.ndarray:

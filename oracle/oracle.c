@@ -604,6 +604,7 @@ int orc_run(const orc_cfg *cfg, int32_t E, orc_batch *b, uint64_t seed_act, uint
 #define ORC_FEAT_C 38
 #define ORC_HIST 7           /* H_hist, the delta stack depth */
 #define ORC_FRAMES 8         /* frames t-7 .. t */
+#define ORC_WINDOW 512       /* scoreboard window of the two temporal tokens */
 
 typedef struct orc_fmem {
     int32_t valid;                                /* 0: no frame recorded yet */
@@ -619,6 +620,10 @@ typedef struct orc_fmem {
     int32_t frame_turn[ORC_FRAMES];
     int32_t own[ORC_FRAMES][ORC_MAX_P][ORC_MAX_CELLS];   /* channel 1 of that frame */
     int32_t enemy[ORC_FRAMES][ORC_MAX_P][ORC_MAX_CELLS]; /* channel 2 of that frame */
+    int32_t n_score;                              /* kept scoreboard records, oldest first */
+    int32_t score_turn[ORC_WINDOW];
+    int32_t opp_land[ORC_WINDOW][ORC_MAX_P];      /* land of all of p's enemies at that turn */
+    int64_t opp_army[ORC_WINDOW][ORC_MAX_P];      /* their army total */
 } orc_fmem;
 
 /* An enemy of player p owns the cell: owned, and not by p's team. */
@@ -651,8 +656,11 @@ static int frame_at(const orc_fmem *m, int64_t t)
 }
 
 /* Record the current frame into the memory and write the 38 channels of
- * every player: feat [P][38][H*W]. */
-static void features_env(const orc_env *s, orc_fmem *m, float *feat)
+ * every player, feat [P][38][H*W], and, if tok is not NULL, the two
+ * temporal tokens of every player (Section V-A, network architecture):
+ * tok [P][2][512], row 0 the enemies' army total and row 1 their land for
+ * the turns t-511 .. t (oldest first; 0 for a turn with no record). */
+static void features_env(const orc_env *s, orc_fmem *m, float *feat, float *tok)
 {
     const int H = s->H, W = s->W, HW = H * W, P = s->P;
     int vis[ORC_MAX_P][ORC_MAX_CELLS];
@@ -764,20 +772,59 @@ static void features_env(const orc_env *s, orc_fmem *m, float *feat)
             }
         }
     }
+
+    /* scoreboard record of this turn (a repeated turn replaces its entry) */
+    int rs;
+    if (m->n_score > 0 && m->score_turn[m->n_score - 1] == s->turn) {
+        rs = m->n_score - 1;
+    } else {
+        if (m->n_score == ORC_WINDOW) {
+            memmove(&m->score_turn[0], &m->score_turn[1], sizeof(int32_t) * (ORC_WINDOW - 1));
+            memmove(&m->opp_land[0], &m->opp_land[1], sizeof(m->opp_land[0]) * (ORC_WINDOW - 1));
+            memmove(&m->opp_army[0], &m->opp_army[1], sizeof(m->opp_army[0]) * (ORC_WINDOW - 1));
+            m->n_score--;
+        }
+        rs = m->n_score++;
+    }
+    m->score_turn[rs] = s->turn;
+    for (int p = 0; p < P; p++) {
+        m->opp_land[rs][p] = 0;
+        m->opp_army[rs][p] = 0;
+        for (int q = 0; q < P; q++) {
+            if (q != p && !in_team(s, q, p)) {
+                m->opp_land[rs][p] += land[q];
+                m->opp_army[rs][p] += army[q];
+            }
+        }
+    }
+    if (tok == NULL) return;
+    const int64_t first = (int64_t)s->turn - (ORC_WINDOW - 1);
+    for (int p = 0; p < P; p++) {
+        float *tp = tok + (size_t)p * 2 * ORC_WINDOW;
+        for (int j = 0; j < 2 * ORC_WINDOW; j++) tp[j] = 0.0f;
+        for (int i = 0; i < m->n_score; i++) {
+            const int64_t j = (int64_t)m->score_turn[i] - first;
+            if (j < 0 || j >= ORC_WINDOW) continue;
+            tp[j] = (float)m->opp_army[i][p];
+            tp[ORC_WINDOW + j] = (float)m->opp_land[i][p];
+        }
+    }
 }
 
 /* Size of one env's feature memory; the caller zero-fills E of them once. */
 int64_t orc_fmem_bytes(void) { return (int64_t)sizeof(orc_fmem); }
 
-/* Features of every env: mem [E] orc_fmem (updated), feat [E][P][38][H*W]. */
-int orc_features_batch(const orc_cfg *cfg, int32_t E, const orc_batch *b, void *mem, float *feat)
+/* Features of every env: mem [E] orc_fmem (updated), feat [E][P][38][H*W],
+ * tok [E][P][2][512] or NULL. */
+int orc_features_batch(const orc_cfg *cfg, int32_t E, const orc_batch *b, void *mem, float *feat, float *tok)
 {
     orc_env s;
     if (!cfg_ok(cfg)) return -1;
     const size_t per = (size_t)cfg->P * ORC_FEAT_C * cfg->H * cfg->W;
     for (int e = 0; e < E; e++) {
         load_env(&s, cfg, b, e);
-        features_env(&s, (orc_fmem *)mem + e, feat + (size_t)e * per);
+        features_env(&s, (orc_fmem *)mem + e, feat + (size_t)e * per,
+                     tok ? tok + (size_t)e * cfg->P * 2 * ORC_WINDOW : NULL);
     }
     return 0;
 }

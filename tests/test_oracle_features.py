@@ -123,6 +123,28 @@ def definitional(frames, mode, P, H, W):
     return out
 
 
+def definitional_tokens(frames, mode, P, H, W):
+    """Temporal tokens of the last frame: for each player the enemies' army
+    total (row 0) and land (row 1) at turns t-511 .. t, 0 where no frame of
+    the episode has that turn."""
+    cur = frames[-1]
+    ep = [f for f in frames if f["episode"] == cur["episode"]]
+    turn = int(cur["turn"])
+    win = oracle.TOKEN_WINDOW
+    tok = np.zeros((P, 2, win), np.float32)
+    for f in ep:                                   # later records of a turn win
+        j = int(f["turn"]) - (turn - win + 1)
+        if not 0 <= j < win:
+            continue
+        owner, army = f["owner"], f["army"].astype(np.int64)
+        for p in range(P):
+            enemies = [q for q in range(P) if q not in team_of(mode, p, P)]
+            sel = np.isin(owner, enemies)
+            tok[p, 0, j] = np.float32(army[sel].sum())
+            tok[p, 1, j] = np.float32(sel.sum())
+    return tok
+
+
 def env_state(st, e):
     return {k: st[k][e].copy() for k in ("owner", "army", "type", "turn", "episode")}
 
@@ -138,12 +160,15 @@ def run_case(H, W, mode, P, E, steps, seed, record_every=1, repeat_every=0, **pr
         if t % record_every == 0:
             for e in range(E):
                 hist[e].append(env_state(st, e))
-            f = oracle.features(cfg, st, mem)
+            f, tok = oracle.features(cfg, st, mem, tokens=True)
             if repeat_every and t % repeat_every == 0:          # recording a turn twice changes nothing
-                assert np.array_equal(oracle.features(cfg, st, mem), f)
+                f2, tok2 = oracle.features(cfg, st, mem, tokens=True)
+                assert np.array_equal(f2, f) and np.array_equal(tok2, tok)
             for e in range(E):
                 want = definitional(hist[e], mode, P, H, W)
                 np.testing.assert_array_equal(f[e], want, err_msg=f"step {t} env {e}")
+                np.testing.assert_array_equal(tok[e], definitional_tokens(hist[e], mode, P, H, W),
+                                              err_msg=f"tokens step {t} env {e}")
                 checked += 1
         oracle.step(cfg, st, oracle.sample(cfg, st, seed + 1, t))
     return checked, st
@@ -225,3 +250,26 @@ def test_features_closed_forms_and_obs_agreement():
         assert np.all(f[:, :, 15] == (st["turn"] % 50 / 50.0).astype(np.float32)[:, None, None, None])
         # own army = army on own cells; own + ally + enemy + neutral (visible) = armies channel
         assert np.array_equal(f[:, :, 1], f[:, :, 1] * f[:, :, 10])
+
+
+def test_tokens_window_slides_past_512_turns():
+    """A 1v1 episode longer than the window: the oldest turns drop out.  Each
+    turn is recorded twice, which must not shorten the window."""
+    cfg = oracle.Config(H=8, W=8, mode=oracle.MODE_1V1, P=2, mountain_thresh=workloads.mountain_thresh(1, 5),
+                        cities_min=1, cities_max=2, city_army_min=40, city_army_max=50, min_general_dist=6,
+                        auto_reset=0, seed=13, env_base=0)
+    st, _ = oracle.reset(cfg, 3)
+    mem = oracle.feature_memory(3)
+    hist = [[] for _ in range(3)]
+    for t in range(700):
+        for e in range(3):
+            hist[e].append({k: st[k][e].copy() for k in ("owner", "army", "type", "turn", "episode")})
+        oracle.features(cfg, st, mem)
+        f, tok = oracle.features(cfg, st, mem, tokens=True)
+        if t in (0, 1, 511, 512, 600, 699):
+            for e in range(3):
+                np.testing.assert_array_equal(tok[e], definitional_tokens(hist[e], cfg.mode, 2, 8, 8))
+        oracle.step(cfg, st, oracle.sample(cfg, st, 14, t))
+    assert (st["turn"] >= 600).any()
+    e = int(np.argmax(st["turn"]))
+    assert tok[e, 0, 1, -1] == f[e, 0, 18, 0, 0]           # newest token entry = current scoreboard channel
