@@ -50,7 +50,9 @@ class _Cfg(ctypes.Structure):
                 ("cities_min", ctypes.c_int32), ("cities_max", ctypes.c_int32),
                 ("city_army_min", ctypes.c_int32), ("city_army_max", ctypes.c_int32),
                 ("min_general_dist", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("pregrow", ctypes.c_int32), ("seed", ctypes.c_uint64), ("env_base", ctypes.c_uint64)]
+                ("pregrow", ctypes.c_int32), ("seed", ctypes.c_uint64), ("env_base", ctypes.c_uint64),
+                ("generator", ctypes.c_int32), ("max_general_dist", ctypes.c_int32),
+                ("castle_radius", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _Batch(ctypes.Structure):
@@ -102,11 +104,15 @@ class Config:
     pregrow: int = 0
     seed: int = 0
     env_base: int = 0
+    generator: int = 0            # 0 synthetic (R14), 1 official rules (R18)
+    max_general_dist: int = 0     # R18 spawn-distance cap (0: none)
+    castle_radius: int = 6        # R18
 
     def _c(self) -> _Cfg:
         return _Cfg(self.H, self.W, self.mode, self.P, self.mountain_thresh, self.cities_min,
                     self.cities_max, self.city_army_min, self.city_army_max,
-                    self.min_general_dist, self.auto_reset, self.pregrow, self.seed, self.env_base)
+                    self.min_general_dist, self.auto_reset, self.pregrow, self.seed, self.env_base,
+                    self.generator, self.max_general_dist, self.castle_radius, 0)
 
 
 def empty_state(cfg: Config, E: int) -> dict:

@@ -10,7 +10,7 @@
  * host-state format (plain arrays) and the seeds.
  *
  * The paper leaves many details open.  Every such gap is filled by a numbered
- * reading (R1..R17) that the HIP path follows too; the readings are listed,
+ * reading (R1..R18) that the HIP path follows too; the readings are listed,
  * with the passage each one rests on, in the design notes at the repository
  * root.  Parts of this file that no external fact pins carry the marker
  * "parity unpinned" below: the move order (R5), the per-cell halving on
@@ -46,6 +46,10 @@ typedef struct orc_cfg {
     int32_t pregrow;               /* pre-grown generals on env%4==0, episode 0 */
     uint64_t seed;                 /* map seed */
     uint64_t env_base;             /* global id of env 0 of the batch */
+    int32_t generator;             /* 0: synthetic generator (R14); 1: official rules (R18) */
+    int32_t max_general_dist;      /* R18: cap on the BFS spawn distance (0 = none; curriculum) */
+    int32_t castle_radius;         /* R18: a castle within this BFS distance of every general */
+    int32_t pad;
 } orc_cfg;
 
 /* Public host-state format: env-major plain arrays. */
@@ -141,6 +145,116 @@ static int in_team(const orc_env *s, int owner, int p)
     return owner == p || (owner >= 0 && is_ally(s, owner, p));
 }
 
+/* BFS distance from src over non-mountain cells, 4-connected (-1: not
+ * reachable). */
+static void bfs_dist(const orc_env *s, int src, int *dist)
+{
+    const int H = s->H, W = s->W, HW = H * W;
+    int queue[ORC_MAX_CELLS];
+    for (int c = 0; c < HW; c++) dist[c] = -1;
+    int qh = 0, qt = 0;
+    dist[src] = 0;
+    queue[qt++] = src;
+    while (qh < qt) {
+        int c = queue[qh++];
+        int r = c / W, col = c % W;
+        int nb[4][2] = { { r - 1, col }, { r + 1, col }, { r, col - 1 }, { r, col + 1 } };
+        for (int k = 0; k < 4; k++) {
+            int nr = nb[k][0], nc = nb[k][1];
+            if (nr < 0 || nr >= H || nc < 0 || nc >= W) continue;
+            int d = nr * W + nc;
+            if (s->type[d] == T_MOUNTAIN || dist[d] >= 0) continue;
+            dist[d] = dist[c] + 1;
+            queue[qt++] = d;
+        }
+    }
+}
+
+/* ======================================================================
+ * The official generator (Section IV-A: 20% mountains, 9..11 neutral castles
+ * of 40..50 units, generals at least 17 steps apart, a neutral castle within
+ * radius 6 of every general) with the spawn-distance cap of the curriculum
+ * (Section V-C); reading R18.  Same stream and attempt structure as the
+ * synthetic generator: G1 and G2 unchanged; every distance is a BFS over
+ * non-mountain cells; each further general is a pick over the cells whose
+ * distance to every earlier general lies in [min, max]; after the castle
+ * count, every general in order that has no castle within the radius gets
+ * one picked among the plain cells within it, then the remaining castles go
+ * anywhere.  Returns 1 on success (state filled), 0 if this attempt fails.
+ * parity unpinned: the draw order is a reading.
+ * ==================================================================== */
+static int mapgen_official_attempt(orc_env *s, const orc_cfg *cfg, uint64_t env_id, uint32_t episode, int attempt)
+{
+    const int H = cfg->H, W = cfg->W, HW = H * W, P = cfg->P;
+    int list[ORC_MAX_CELLS];
+    int dist[ORC_MAX_P][ORC_MAX_CELLS];
+    int g[ORC_MAX_P];
+    const uint32_t T = attempt < 64 ? cfg->mountain_thresh : 0u;
+    uint64_t j = 0;
+    for (int c = 0; c < HW; c++) {
+        uint32_t r = orc_draw(cfg->seed, D_MAPGEN, env_id, episode, (uint64_t)attempt, j++);
+        s->type[c] = (r < T) ? T_MOUNTAIN : T_PLAIN;
+        s->owner[c] = -1;
+        s->army[c] = 0;
+    }
+    int n = 0;
+    for (int c = 0; c < HW; c++)
+        if (s->type[c] != T_MOUNTAIN) list[n++] = c;
+    if (n == 0) return 0;
+    g[0] = list[pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++), (uint32_t)n)];
+    bfs_dist(s, g[0], dist[0]);
+    for (int i = 1; i < P; i++) {
+        n = 0;
+        for (int c = 0; c < HW; c++) {
+            int good = 1;
+            for (int k = 0; k < i; k++) {
+                const int d = dist[k][c];
+                if (d < 0 || d < cfg->min_general_dist || c == g[k] ||
+                    (cfg->max_general_dist > 0 && d > cfg->max_general_dist)) { good = 0; break; }
+            }
+            if (good) list[n++] = c;
+        }
+        if (n == 0) return 0;
+        g[i] = list[pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++), (uint32_t)n)];
+        bfs_dist(s, g[i], dist[i]);
+    }
+    for (int i = 0; i < P; i++) s->type[g[i]] = T_GENERAL;
+    int ncastles = cfg->cities_min + (int)pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++),
+                                               (uint32_t)(cfg->cities_max - cfg->cities_min + 1));
+    int placed = 0;
+    for (int i = 0; i < P; i++) {
+        int near = 0;
+        for (int c = 0; c < HW; c++)
+            if (s->type[c] == T_CASTLE && dist[i][c] >= 0 && dist[i][c] <= cfg->castle_radius) near = 1;
+        if (near) continue;
+        n = 0;
+        for (int c = 0; c < HW; c++)
+            if (s->type[c] == T_PLAIN && dist[i][c] >= 1 && dist[i][c] <= cfg->castle_radius) list[n++] = c;
+        if (n == 0) return 0;
+        int c = list[pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++), (uint32_t)n)];
+        s->type[c] = T_CASTLE;
+        s->army[c] = cfg->city_army_min + (int32_t)pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++),
+                                                         (uint32_t)(cfg->city_army_max - cfg->city_army_min + 1));
+        placed++;
+    }
+    for (int t = placed; t < ncastles; t++) {
+        n = 0;
+        for (int c = 0; c < HW; c++)
+            if (s->type[c] == T_PLAIN) list[n++] = c;
+        if (n == 0) break;
+        int c = list[pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++), (uint32_t)n)];
+        s->type[c] = T_CASTLE;
+        s->army[c] = cfg->city_army_min + (int32_t)pick(orc_draw(cfg->seed, D_MAPGEN, env_id, episode, attempt, j++),
+                                                         (uint32_t)(cfg->city_army_max - cfg->city_army_min + 1));
+    }
+    for (int i = 0; i < P; i++) {
+        s->owner[g[i]] = (int8_t)i;
+        s->army[g[i]] = 1;
+        s->gpos[i] = (int16_t)g[i];
+    }
+    return 1;
+}
+
 /* ======================================================================
  * Map generation (Section IV-A, with the generator parameters of the
  * synthetic workloads; reading R14).  Returns the attempt that succeeded
@@ -157,6 +271,14 @@ static int mapgen(orc_env *s, const orc_cfg *cfg, uint64_t env_id, uint32_t epis
 
     s->H = H; s->W = W; s->P = P; s->mode = cfg->mode;
     for (int attempt = 0; attempt < 128; attempt++) {
+        if (cfg->generator == 1) {
+            if (!mapgen_official_attempt(s, cfg, env_id, episode, attempt)) continue;
+            s->turn = 0;
+            s->episode = episode;
+            s->alive = (uint8_t)((1u << P) - 1u);
+            s->finished = 0;
+            return attempt;
+        }
         uint32_t T = attempt < 64 ? cfg->mountain_thresh : 0u;
         uint64_t j = 0;
         /* G1: mountains, one draw per cell in row-major order */
