@@ -35,8 +35,18 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2606_23348_amd/csrc/kernels.hip", "paper_2606_23348_amd/csrc/device.hpp"]
+KERNEL_SOURCES = ["paper_2606_23348_amd/csrc/kernels.hip", "paper_2606_23348_amd/csrc/features.hip",
+                  "paper_2606_23348_amd/csrc/device.hpp", "paper_2606_23348_amd/csrc/internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+EXTRAS = ("step_alone", "features", "copy", "rollout", "served", "pool", "served_mix")
+
+
+_T0 = time.perf_counter()
+
+
+def log(msg: str):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -122,34 +132,68 @@ def feature_bytes(wl) -> dict:
     the 7 earlier frames of the ring (6 bytes per cell each); it writes the
     per-player memory, this frame's ring slot, the header and the float32
     [P][38][H][W] features."""
-    HW, P = wl.H * wl.W, wl.P
+    HW, P, win = wl.H * wl.W, wl.P, 512
     read = HW * 6 + 32 + 64 + 9 * P * HW + 7 * 6 * HW
-    write = 9 * P * HW + 6 * HW + 40 + 38 * 4 * P * HW
-    return {"read": read, "write": write, "total": read + write}
+    write = 9 * P * HW + 6 * HW + 40 + 38 * 4 * P * HW + 4 + 12 * P
+    tok_read = win * 4 + win * 12 * P            # the scoreboard ring, for the 512-turn windows
+    tok_write = 2 * win * 4 * P
+    return {"read": read, "write": write, "total": read + write,
+            "total_with_tokens": read + write + tok_read + tok_write}
 
 
 def run_features(b, wl, torch, stream, steps: int, first_step: int) -> dict:
     """The 38-channel features (gen_features) after every fused step; only
     the features launch lies between the events."""
-    b.features()                                  # allocates the memory and the output
+    b.features(tokens=True)                       # allocates the memory and the outputs
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     for t in range(steps):
         b.step_sample(wl.actor_seed, first_step + t)
         ev0[t].record(stream)
-        b.features()
+        b.features(tokens=True)
         ev1[t].record(stream)
     torch.cuda.synchronize()
     ms = np.array([ev0[t].elapsed_time(ev1[t]) for t in range(steps)])
     by = feature_bytes(wl)
-    out = {"kernel": "k_features (gen_features)", "steps": steps, "kernel_ms_mean": float(ms.mean()),
-           "kernel_ms_p50": float(np.percentile(ms, 50)), "frames_per_s": b.n_envs / (float(ms.mean()) / 1e3),
-           "algorithmic_bytes_per_frame": by["total"],
-           "achieved_gbs": by["total"] * b.n_envs / (float(ms.mean()) / 1e3) / 1e9}
+    out = {"kernel": "k_features (gen_features, with the temporal tokens)", "steps": steps,
+           "kernel_ms_mean": float(ms.mean()), "kernel_ms_p50": float(np.percentile(ms, 50)),
+           "frames_per_s": b.n_envs / (float(ms.mean()) / 1e3),
+           "algorithmic_bytes_per_frame": by["total_with_tokens"],
+           "achieved_gbs": by["total_with_tokens"] * b.n_envs / (float(ms.mean()) / 1e3) / 1e9}
     out["frac_of_peak"] = out["achieved_gbs"] / HBM_PEAK_GBS
-    b.feat = b.fmem = None
+    out["traffic"] = traffic_for("features-" + wl.name, b.n_envs)
+    b.feat = b.fmem = b.tokens = None
     torch.cuda.empty_cache()
     return out
+
+
+def run_rollout(gen, torch, n_envs: int = 512, n_steps: int = 512) -> dict:
+    """The paper's training setting (512 envs x 512-step rollouts, 1v1 on the
+    official 23x23 rules): features, random actor and step per step, into a
+    rollout buffer; one timed rollout after a short warm-up."""
+    H = W = 23
+    params = gen.make_params(0, 2, generator=1, min_general_dist=17, castle_radius=6)
+    b = gen.Batch(n_envs, H, W, 0, params, seed=7)
+    out = b.rollout(16, 1007, 0, tokens=True)          # warm-up
+    del out
+    torch.cuda.empty_cache()
+    big = {"feat": torch.empty((n_steps, n_envs, 2, 38, H, W), dtype=torch.float32, device="cuda"),
+           "tokens": torch.empty((n_steps, n_envs, 2, 2, 512), dtype=torch.float32, device="cuda"),
+           "actions": torch.empty((n_steps, n_envs, 2), dtype=torch.int32, device="cuda"),
+           "rewards": torch.empty((n_steps, n_envs, 2), dtype=torch.int32, device="cuda"),
+           "dones": torch.empty((n_steps, n_envs), dtype=torch.uint8, device="cuda")}
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.rollout(n_steps, 1007, 16, tokens=True, out=big)
+    e1.record()
+    torch.cuda.synchronize()
+    s_ = e0.elapsed_time(e1) / 1e3
+    del big, b
+    torch.cuda.empty_cache()
+    return {"workload": f"rollout 1v1 {H}x{W} official rules, {n_envs} envs x {n_steps} steps "
+                        "(features + tokens + random actor + step)",
+            "ms_per_rollout": s_ * 1e3, "frames_per_s": n_envs * n_steps / s_, "launches": 2 * n_steps + 1}
 
 
 def pool_bytes_per_frame(specs) -> float:
@@ -173,7 +217,11 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
                              city_army_max=wl.city_army_max, auto_reset=wl.auto_reset)
     best, table = ({"waves_per_group": 1, "grid": 0, "order": 0}, {})
     if tune_it:
-        best, table = tuner.tune(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, steps=8, cache_path=None)
+        n_cus = torch.cuda.get_device_properties(0).multi_processor_count
+        cands = [{"waves_per_group": w, "grid": gr, "order": o} for o in (0, 1) for w in (1, 2)
+                 for gr in (0, 8 * n_cus)]
+        best, table = tuner.tune(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, steps=8, cache_path=None,
+                                 cands=cands, progress=log)
     pool = gen.Pool(specs, common, seed=wl.seed)
     s = torch.cuda.Stream()
     K = 10
@@ -208,6 +256,7 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
         b = gen.Batch(n, int(H), int(W), int(mode), prm, seed=wl.seed, env_base=first)
         b.sample(wl.actor_seed, 0)
         batches.append(b)
+    log(f"pool: {len(uniq)} per-bucket batches built")
     bsteps = 5
     for b in batches:
         b.step_sample(wl.actor_seed, 1)
@@ -305,6 +354,8 @@ def main() -> int:
                     help="only run N copies of 1 GiB (counter calibration run) and exit")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain workload only (no served, pooled or copy-ceiling legs)")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated subset of the extra legs: " + ",".join(EXTRAS))
     ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
@@ -385,16 +436,36 @@ def main() -> int:
                      "algorithmic_bytes_per_frame": by["step"],
                      "frames_per_launch": E},
     }
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    unknown = legs - set(EXTRAS)
+    if unknown:
+        print(f"unknown extra legs {sorted(unknown)}", file=sys.stderr)
+        return 2
+    log(f"headline {wl.name}: {value / 1e6:.1f} M frames/s")
+    if "step_alone" in legs:
         out["step_alone"] = run_step_alone(b, wl, torch, stream, min(K, 1000), W + K + 1)
+    if "features" in legs:
+        log("features leg")
         out["features"] = run_features(b, wl, torch, stream, 100, W + K + min(K, 1000) + 1)
-        del b
-        torch.cuda.empty_cache()
+    del b
+    torch.cuda.empty_cache()
+    if "copy" in legs:
+        log("copy ceiling")
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(torch)
+    if "rollout" in legs:
+        log("rollout leg")
+        out["rollout"] = run_rollout(gen, torch)
+    if "served" in legs:
+        log("served leg")
         out["served"] = run_served_c2(gen, torch, args.served_seconds)
+    if "pool" in legs:
+        log("pool leg")
         out["pool"] = run_pool(gen, torch, 200, not args.no_tune)
+    if "served_mix" in legs:
+        log("served mix leg")
         out["served_mix"] = run_served_mix(gen, torch, args.served_seconds)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_envs, args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0

@@ -81,7 +81,14 @@ typedef struct gen_params {
     int32_t auto_reset;         /* 1: a finished game restarts on the next map in the same step */
     int32_t pregrow;            /* 1: at episode 0, envs with global id % 4 == 0 start
                                    each general at 100000 + U{0..900000} */
-    int32_t reserved[7];        /* must be zero */
+    int32_t generator;          /* 0: synthetic generator (Manhattan spacing, cities
+                                   anywhere); 1: the official rules (Section IV-A):
+                                   spacing in BFS steps over non-mountain cells and a
+                                   castle within castle_radius steps of every general */
+    int32_t max_general_dist;   /* generator 1: cap on the BFS distance between generals
+                                   (the spawn-distance curriculum, Section V-C); 0 = none */
+    int32_t castle_radius;      /* generator 1: BFS radius of the guaranteed castle (6) */
+    int32_t reserved[4];        /* must be zero */
 } gen_params;
 
 /* Descriptor of one batch of identical envs living in one device buffer.
@@ -131,8 +138,11 @@ int gen_version(void);
  * pointer stays valid until the next call on the same thread. */
 const char *gen_last_error(void);
 
-/* Defaults of the paper's generator (Section IV-A): 20% mountains, 9..11
- * castles of 40..50 units, generals at least 9 apart, auto-reset on. */
+/* Defaults (Section IV-A): 20% mountains, 9..11 castles of 40..50 units,
+ * auto-reset on, the synthetic generator with generals at least 9 apart
+ * (Manhattan); castle_radius 6.  For the official rules set generator = 1
+ * and min_general_dist = 17; for a curriculum stage, min_general_dist = 1
+ * and max_general_dist = the stage's cap. */
 int gen_default_params(int32_t mode, int32_t n_players, gen_params *out);
 
 /* Compute the device layout of n_envs envs of H x W (3..32 each side) in
@@ -216,9 +226,14 @@ int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
  * calling twice on the same state returns the same tensor.  Values are
  * exact integers converted to float32 (round to nearest even), except 15,
  * 21, 22 and 23 (computed in double, rounded once to float32).
+ * The two temporal tokens of the network input (Section V-A) come with the
+ * same call: float32 [E][P][2][512], for each player the army total (row 0)
+ * and the land (row 1) of all its enemies at turns t-511 .. t, oldest
+ * first, 0 for a turn that was not recorded.
  * ---------------------------------------------------------------------- */
 #define GEN_FEAT_CHANNELS 38
 #define GEN_FEAT_HISTORY 7
+#define GEN_TOKEN_WINDOW 512
 
 /* Device bytes of the feature memory of the batch `st` (0 if st is invalid).
  * The caller allocates it (256-byte aligned) and zero-fills it once before
@@ -226,8 +241,26 @@ int gen_observe(const gen_state *st, uint8_t *d_obs, void *stream);
 uint64_t gen_feat_mem_bytes(const gen_state *st);
 
 /* Record the current state of every env into d_mem and write the features
- * d_feat float32 [E][P][38][H][W].  GEN_ENOMEM if mem_bytes is too small. */
-int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, void *stream);
+ * d_feat float32 [E][P][38][H][W] and, if d_tokens is not NULL, the temporal
+ * tokens d_tokens float32 [E][P][2][512].  GEN_ENOMEM if mem_bytes is too
+ * small. */
+int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, float *d_tokens,
+                 void *stream);
+
+/* A rollout for a learner (Appendix D, training hyperparameters: 512 envs x
+ * 512 steps per iteration),
+ * driven by the random actor in place of a policy: for t = 0 .. n_steps-1,
+ *   features of the current state  -> d_feat   [t][E][P][38][H][W]
+ *   (and tokens if not NULL)       -> d_tokens [t][E][P][2][512]
+ *   actor draws, step index step0+t -> d_actions [t][E][P]
+ *   one step                        -> d_rewards [t][E][P], d_dones [t][E]
+ * exactly as gen_features, gen_sample_actions and gen_step called in that
+ * order (no 8-channel observation is written).  2 launches per step on
+ * `stream` (capture the stream into a HIP graph to replay whole rollouts).
+ * The batch and d_mem advance by n_steps steps. */
+int gen_rollout(const gen_state *st, void *d_mem, uint64_t mem_bytes, int32_t n_steps, uint64_t actor_seed,
+                uint64_t step0, float *d_feat, float *d_tokens, int32_t *d_actions, int32_t *d_rewards, uint8_t *d_dones,
+                void *stream);
 
 /* Blocking copies between the device buffer and the public host format
  * (synchronises `stream`).  gen_set_state rejects (GEN_EINVAL) contents the

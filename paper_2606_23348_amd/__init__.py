@@ -33,7 +33,9 @@ class gen_params(ctypes.Structure):
                 ("cities_min", ctypes.c_int32), ("cities_max", ctypes.c_int32),
                 ("city_army_min", ctypes.c_int32), ("city_army_max", ctypes.c_int32),
                 ("min_general_dist", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
-                ("pregrow", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("pregrow", ctypes.c_int32), ("generator", ctypes.c_int32),
+                ("max_general_dist", ctypes.c_int32), ("castle_radius", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class gen_state(ctypes.Structure):
@@ -112,7 +114,8 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_step_sample.argtypes = [P(gen_state), vp, u64, u64, vp, vp, vp, vp, vp, vp]
     L.gen_observe.argtypes = [P(gen_state), vp, vp]
     L.gen_feat_mem_bytes.argtypes, L.gen_feat_mem_bytes.restype = [P(gen_state)], u64
-    L.gen_features.argtypes = [P(gen_state), vp, u64, vp, vp]
+    L.gen_features.argtypes = [P(gen_state), vp, u64, vp, vp, vp]
+    L.gen_rollout.argtypes = [P(gen_state), vp, u64, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.gen_get_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_set_state.argtypes = [P(gen_state), P(gen_host_state), vp]
     L.gen_get_envs.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
@@ -138,7 +141,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_server_drive.argtypes = [vp, i32, i32, vp, vp, P(gen_params), u64, u64, vp, i32, ctypes.c_int64, i32,
                                    P(gen_server_stats)]
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
-              "gen_observe", "gen_features", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
+              "gen_observe", "gen_features", "gen_rollout", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
               "gen_pool_get_env", "gen_server_create", "gen_server_destroy", "gen_server_open",
@@ -256,6 +259,7 @@ def _host_struct(h: dict) -> gen_host_state:
 
 
 FEAT_CHANNELS = 38
+TOKEN_WINDOW = 512
 
 
 def gen_feat_mem_bytes(st: gen_state) -> int:
@@ -265,9 +269,16 @@ def gen_feat_mem_bytes(st: gen_state) -> int:
     return n
 
 
-def gen_features(st: gen_state, mem, feat, stream=None):
+def gen_features(st: gen_state, mem, feat, tokens=None, stream=None):
     _check(lib().gen_features(ctypes.byref(st), _ptr(mem), mem.numel() * mem.element_size(), _ptr(feat),
-                              _stream(stream)))
+                              _ptr(tokens), _stream(stream)))
+
+
+def gen_rollout(st: gen_state, mem, n_steps: int, actor_seed: int, step0: int, feat, actions, rewards, dones,
+                tokens=None, stream=None):
+    _check(lib().gen_rollout(ctypes.byref(st), _ptr(mem), mem.numel() * mem.element_size(), n_steps, actor_seed,
+                             step0, _ptr(feat), _ptr(tokens), _ptr(actions), _ptr(rewards), _ptr(dones),
+                             _stream(stream)))
 
 
 def gen_get_state(st: gen_state, stream=None) -> dict:
@@ -311,7 +322,7 @@ class Batch:
         self.dones = torch.zeros(n_envs, dtype=torch.uint8, device=device)
         self.land = torch.zeros((n_envs, P), dtype=torch.int32, device=device) if scoreboard else None
         self.army = torch.zeros((n_envs, P), dtype=torch.int64, device=device) if scoreboard else None
-        self.feat = self.fmem = None           # 38-channel features, allocated by features()
+        self.feat = self.fmem = self.tokens = None   # 38-channel features, allocated by features()
         self.st = gen_reset(seed, env_base, n_envs, H, W, mode, params, self.buf, self.obs, stream)
 
     def sample(self, actor_seed: int, step_idx: int, stream=None):
@@ -327,17 +338,43 @@ class Batch:
     def observe(self, stream=None):
         gen_observe(self.st, self.obs, stream)
 
-    def features(self, stream=None):
+    def features(self, tokens: bool = False, stream=None):
         """The 38-channel features float32 [E][P][38][H][W] of the current
-        state into self.feat (allocated, with its zero-filled memory, on the
-        first call).  Call once after reset and after every step."""
-        if getattr(self, "feat", None) is None:
-            import torch
-            dev = self.buf.device
+        state into self.feat and, with tokens=True, the temporal tokens
+        float32 [E][P][2][512] into self.tokens (allocated, with the
+        zero-filled memory, on first use).  Call once after reset and after
+        every step."""
+        import torch
+        dev = self.buf.device
+        if self.feat is None:
             self.fmem = torch.zeros(gen_feat_mem_bytes(self.st), dtype=torch.uint8, device=dev)
             self.feat = torch.zeros((self.n_envs, self.P, FEAT_CHANNELS, self.H, self.W), dtype=torch.float32,
                                     device=dev)
-        gen_features(self.st, self.fmem, self.feat, stream)
+        if tokens and self.tokens is None:
+            self.tokens = torch.zeros((self.n_envs, self.P, 2, TOKEN_WINDOW), dtype=torch.float32, device=dev)
+        gen_features(self.st, self.fmem, self.feat, self.tokens if tokens else None, stream)
+
+    def rollout(self, n_steps: int, actor_seed: int, step0: int, tokens: bool = False, out: dict | None = None,
+                stream=None) -> dict:
+        """n_steps of features -> random actor -> step into a rollout buffer
+        (allocated unless `out` holds one from an earlier call):
+        feat [T][E][P][38][H][W], tokens [T][E][P][2][512] (tokens=True),
+        actions/rewards [T][E][P], dones [T][E]."""
+        import torch
+        dev = self.buf.device
+        if self.fmem is None:
+            self.fmem = torch.zeros(gen_feat_mem_bytes(self.st), dtype=torch.uint8, device=dev)
+        E, P, T = self.n_envs, self.P, n_steps
+        if out is None:
+            out = {"feat": torch.empty((T, E, P, FEAT_CHANNELS, self.H, self.W), dtype=torch.float32, device=dev),
+                   "actions": torch.empty((T, E, P), dtype=torch.int32, device=dev),
+                   "rewards": torch.empty((T, E, P), dtype=torch.int32, device=dev),
+                   "dones": torch.empty((T, E), dtype=torch.uint8, device=dev)}
+            if tokens:
+                out["tokens"] = torch.empty((T, E, P, 2, TOKEN_WINDOW), dtype=torch.float32, device=dev)
+        gen_rollout(self.st, self.fmem, T, actor_seed, step0, out["feat"], out["actions"], out["rewards"],
+                    out["dones"], out.get("tokens"), stream)
+        return out
 
     def get_state(self, stream=None) -> dict:
         return gen_get_state(self.st, stream)

@@ -60,7 +60,12 @@ int check_params(const gen_params &p, int P, int HW)
         return fail(GEN_EINVAL, "min_general_dist %d outside [0, 64]", p.min_general_dist);
     if ((p.auto_reset != 0 && p.auto_reset != 1) || (p.pregrow != 0 && p.pregrow != 1))
         return fail(GEN_EINVAL, "auto_reset and pregrow must be 0 or 1");
-    for (int i = 0; i < 7; ++i)
+    if (p.generator != 0 && p.generator != 1) return fail(GEN_EINVAL, "generator must be 0 or 1");
+    if (p.max_general_dist < 0 || p.max_general_dist > GEN_MAX_CELLS)
+        return fail(GEN_EINVAL, "max_general_dist %d outside [0, %d]", p.max_general_dist, GEN_MAX_CELLS);
+    if (p.castle_radius < 0 || p.castle_radius > 64)
+        return fail(GEN_EINVAL, "castle_radius %d outside [0, 64]", p.castle_radius);
+    for (int i = 0; i < 4; ++i)
         if (p.reserved[i] != 0) return fail(GEN_EINVAL, "gen_params.reserved must be zero");
     (void)P;
     return GEN_OK;
@@ -200,6 +205,9 @@ int gen_default_params(int32_t mode, int32_t n_players, gen_params *out)
     out->min_general_dist = 9;
     out->auto_reset = 1;
     out->pregrow = 0;
+    out->generator = 0;
+    out->max_general_dist = 0;
+    out->castle_radius = 6;
     return ok();
 }
 
@@ -358,12 +366,13 @@ uint64_t gen_feat_mem_bytes(const gen_state *st)
     return (uint64_t)gen::feat_block(st->stride, st->n_players).bytes * (uint64_t)st->n_envs;
 }
 
-int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, void *stream)
+int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_feat, float *d_tokens, void *stream)
 {
     if (check_state(st) != GEN_OK) return GEN_EINVAL;
     if (d_mem == nullptr || !aligned(d_mem, 256))
         return fail(GEN_EINVAL, "d_mem must be a 256-byte aligned device pointer");
     if (d_feat == nullptr || !aligned(d_feat, 4)) return fail(GEN_EINVAL, "d_feat must be a 4-byte aligned device pointer");
+    if (d_tokens != nullptr && !aligned(d_tokens, 4)) return fail(GEN_EINVAL, "d_tokens must be 4-byte aligned");
     const gen::FeatBlock fb = gen::feat_block(st->stride, st->n_players);
     const uint64_t need = (uint64_t)fb.bytes * (uint64_t)st->n_envs;
     if (mem_bytes < need)
@@ -379,8 +388,70 @@ int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_
     a.army = ea.army;
     a.mem = static_cast<uint8_t *>(d_mem);
     a.feat = d_feat;
+    a.tokens = d_tokens;
     hipError_t e = gen::launch_features(a, st->n_envs, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "features launch");
+    return ok();
+}
+
+int gen_rollout(const gen_state *st, void *d_mem, uint64_t mem_bytes, int32_t n_steps, uint64_t actor_seed,
+                uint64_t step0, float *d_feat, float *d_tokens, int32_t *d_actions, int32_t *d_rewards, uint8_t *d_dones,
+                void *stream)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (n_steps < 1) return fail(GEN_EINVAL, "n_steps %d must be positive", n_steps);
+    if (d_mem == nullptr || !aligned(d_mem, 256))
+        return fail(GEN_EINVAL, "d_mem must be a 256-byte aligned device pointer");
+    if (d_feat == nullptr || d_actions == nullptr || d_rewards == nullptr || d_dones == nullptr)
+        return fail(GEN_EINVAL, "d_feat, d_actions, d_rewards and d_dones are required");
+    if (!aligned(d_feat, 4) || !aligned(d_actions, 4) || !aligned(d_rewards, 4) || (d_tokens && !aligned(d_tokens, 4)))
+        return fail(GEN_EINVAL, "misaligned rollout buffer");
+    const gen::FeatBlock fb = gen::feat_block(st->stride, st->n_players);
+    if (mem_bytes < (uint64_t)fb.bytes * (uint64_t)st->n_envs)
+        return fail(GEN_ENOMEM, "feature memory holds %llu bytes, the batch needs %llu", (unsigned long long)mem_bytes,
+                    (unsigned long long)((uint64_t)fb.bytes * (uint64_t)st->n_envs));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t E = (size_t)st->n_envs, P = (size_t)st->n_players, HW = (size_t)st->H * st->W;
+    const size_t f_stride = E * P * GEN_FEAT_CHANNELS * HW, t_stride = E * P * 2 * GEN_TOKEN_WINDOW;
+    const gen::EnvArgs base = env_args(*st);
+
+    gen::SampleArgs sa{};
+    sa.g = base.g;
+    sa.env_base = st->env_base;
+    sa.actor_seed = actor_seed;
+    sa.step_idx = step0;
+    sa.sc = base.sc;
+    sa.owner = base.owner;
+    sa.type = base.type;
+    sa.army = base.army;
+    sa.actions = d_actions;
+    hipError_t e = gen::launch_sample(sa, st->n_envs, s);
+    if (e != hipSuccess) return hip_fail(e, "rollout sample launch");
+    for (int32_t t = 0; t < n_steps; ++t) {
+        gen::FeatArgs fa{};
+        fa.g = base.g;
+        fa.blk = fb;
+        fa.sc = base.sc;
+        fa.owner = base.owner;
+        fa.type = base.type;
+        fa.army = base.army;
+        fa.mem = static_cast<uint8_t *>(d_mem);
+        fa.feat = d_feat + (size_t)t * f_stride;
+        fa.tokens = d_tokens ? d_tokens + (size_t)t * t_stride : nullptr;
+        e = gen::launch_features(fa, st->n_envs, s);
+        if (e != hipSuccess) return hip_fail(e, "rollout features launch");
+        gen::EnvArgs ea = base;
+        ea.actions = d_actions + (size_t)t * E * P;
+        ea.rewards = d_rewards + (size_t)t * E * P;
+        ea.dones = d_dones + (size_t)t * E;
+        if (t + 1 < n_steps) {           // the next step's actions, sampled in the same launch
+            ea.next_actions = d_actions + (size_t)(t + 1) * E * P;
+            ea.actor_seed = actor_seed;
+            ea.step_idx = step0 + (uint64_t)t + 1;
+        }
+        e = gen::launch_step(ea, st->n_envs, s);
+        if (e != hipSuccess) return hip_fail(e, "rollout step launch");
+    }
     return ok();
 }
 

@@ -51,6 +51,7 @@ static_assert(sizeof(PoolDesc) == 32, "pool descriptor is 32 bytes");
 struct GenParamsDev {
     uint32_t thresh;
     int cmin, cmax, amin, amax, dmin, auto_reset, pregrow;
+    int generator, dmax, radius;     // official generator: BFS spacing cap, castle radius
 };
 
 // ---------------------------------------------------------------- wave ops

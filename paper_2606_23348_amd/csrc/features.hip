@@ -56,12 +56,15 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
     const FeatBlock fb = a.blk;
     const int S = g.S, HW = g.HW, P = g.P;
 
-    // LDS: owner [S] | type [S] | army int32 [S] | obm [P][16] | vis [P][16]
+    // LDS: owner [S] | type [S] | army int32 [S] | obm [P][16] | vis [P][16] |
+    //      enemy army total [P] int64 | enemy land [P] int32
     int8_t *Lo = reinterpret_cast<int8_t *>(smem);
     uint8_t *Lt = smem + S;
     int32_t *La = reinterpret_cast<int32_t *>(smem + 2 * S);
     uint64_t *obm = reinterpret_cast<uint64_t *>(smem + 6 * S);
     uint64_t *vis = obm + P * 16;
+    int64_t *opp_army_l = reinterpret_cast<int64_t *>(vis + P * 16);
+    int32_t *opp_land_l = reinterpret_cast<int32_t *>(opp_army_l + P);
 
     const EnvScalars s = a.sc[e];
     {
@@ -107,6 +110,21 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
             armt[p] = (int64_t)(((uint64_t)(uint32_t)readfirst((int)(at >> 32)) << 32) |
                                 (uint32_t)readfirst((int)(uint32_t)at));
         }
+    }
+    // the enemies' totals of each player, kept in LDS for the scoreboard ring
+    // (scalar registers are scarce across the cell loop)
+    if (lane < P) {
+        int32_t ol = 0;
+        int64_t oa = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxP; ++q) {
+            if (q < P && q != lane && !(g.mode == MODE_2V2 && q == (lane ^ 2))) {
+                ol += land[q];
+                oa += armt[q];
+            }
+        }
+        opp_army_l[lane] = oa;
+        opp_land_l[lane] = ol;
     }
     wave_sync();
 
@@ -232,6 +250,49 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         }
     }
 
+    // scoreboard ring (Section V-A: the two temporal tokens): this turn's
+    // enemy totals per player, then the 512-turn windows if asked for
+    const int ts = t & (kTokenWindow - 1);
+    for (int j = lane; j < kTokenWindow; j += kWave) {
+        if (fresh || j == ts)
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(j == ts ? t : -1), rm, 4 * j, (int)fb.tstamp, 0);
+    }
+    if (lane < P) {
+        const int64_t oa = opp_army_l[lane];
+        const int off = lane * kTokenWindow + ts;
+        const u32x2 oav = {(uint32_t)(uint64_t)oa, (uint32_t)((uint64_t)oa >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b64(oav, rm, 8 * off, (int)fb.tarmy, 0);
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)opp_land_l[lane], rm, 4 * off, (int)fb.tland, 0);
+    }
+    if (a.tokens != nullptr) {
+        const Rsrc rt = rsrc(a.tokens + (size_t)e * P * 2 * kTokenWindow, (uint32_t)(P * 2 * kTokenWindow * 4));
+        for (int j = lane; j < kTokenWindow; j += kWave) {
+            const int32_t tau = t - (kTokenWindow - 1) + j;
+            const int sl = tau & (kTokenWindow - 1);
+            const bool now = j == kTokenWindow - 1;          // this turn: from registers
+            const bool have = !now && !fresh && tau >= 0 &&
+                              (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * sl, (int)fb.tstamp, 0) == tau;
+#pragma unroll
+            for (int p = 0; p < kMaxP; ++p) {
+                if (p >= P) break;
+                int64_t oa = 0;
+                int32_t ol = 0;
+                if (now) {
+                    oa = opp_army_l[p];
+                    ol = opp_land_l[p];
+                } else if (have) {
+                    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rm, 8 * (p * kTokenWindow + sl), (int)fb.tarmy, 0);
+                    oa = (int64_t)(((uint64_t)v.y << 32) | v.x);
+                    ol = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (p * kTokenWindow + sl), (int)fb.tland, 0);
+                }
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)oa), rt, 4 * j,
+                                                      4 * (p * 2 * kTokenWindow), kNT);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)ol), rt, 4 * j,
+                                                      4 * (p * 2 * kTokenWindow + kTokenWindow), kNT);
+            }
+        }
+    }
+
     if (lane == 0) {
         hdr[0] = kFeatMagic;
         hdr[1] = s.episode;
@@ -242,7 +303,7 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)
 {
-    const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8);
+    const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8 + 12 * a.g.P);
     hipLaunchKernelGGL(k_features, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
     return hipGetLastError();
 }

@@ -77,9 +77,14 @@ struct ServeReq {
 //   fowner  int8  [8][S]   ring of the last 8 frames, slot = turn mod 8:
 //   fvis    uint8 [8][S]     owner, visibility (bit p: visible to p), army
 //   farmy   int32 [8][S]
+//   tstamp  int32 [512]    scoreboard ring, slot = turn mod 512: turn held (-1: none)
+//   tarmy   int64 [P][512] army total of p's enemies at that turn
+//   tland   int32 [P][512] their land
 struct FeatBlock {
-    uint32_t bits, last, lturn, fowner, fvis, farmy, bytes;
+    uint32_t bits, last, lturn, fowner, fvis, farmy, tstamp, tarmy, tland, bytes;
 };
+
+constexpr int kTokenWindow = 512;
 
 __host__ __device__ inline FeatBlock feat_block(int S, int P)
 {
@@ -90,7 +95,10 @@ __host__ __device__ inline FeatBlock feat_block(int S, int P)
     b.fowner = b.lturn + (uint32_t)(4 * P * S);
     b.fvis = b.fowner + (uint32_t)(8 * S);
     b.farmy = b.fvis + (uint32_t)(8 * S);
-    b.bytes = (b.farmy + (uint32_t)(32 * S) + 255u) & ~255u;
+    b.tstamp = b.farmy + (uint32_t)(32 * S);
+    b.tarmy = b.tstamp + 4u * kTokenWindow;
+    b.tland = b.tarmy + (uint32_t)(8 * P) * kTokenWindow;
+    b.bytes = (b.tland + (uint32_t)(4 * P) * kTokenWindow + 255u) & ~255u;
     return b;
 }
 
@@ -105,6 +113,7 @@ struct FeatArgs {
     const int32_t *army;
     uint8_t *mem;
     float *feat;
+    float *tokens;               // [E][P][2][512] or nullptr
 };
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream);
@@ -134,6 +143,9 @@ inline GenParamsDev prm_of(const gen_params &p)
     d.dmin = p.min_general_dist;
     d.auto_reset = p.auto_reset;
     d.pregrow = p.pregrow;
+    d.generator = p.generator;
+    d.dmax = p.max_general_dist;
+    d.radius = p.castle_radius;
     return d;
 }
 

@@ -54,7 +54,110 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
 }
 
 // ---------------------------------------------------------------- map generation
-// Section IV-A generator family (reading R14).  Executed by the whole wave
+// Cells within BFS distance r of `src` (4-neighbour steps over the passable
+// bitmap), for up to three radii in one sweep: lane w < NW gets word w of
+// each set.  r < 0 means unlimited (the connected component).  Layer by
+// layer bitmap dilation (like the fog, with 4 instead of 8 neighbours) until
+// the last requested radius or a fixpoint.  Every lane must call it.
+struct Reach3 { uint64_t a, b, c; };
+
+__device__ Reach3 bfs_reach(const uint64_t *pass, int src, int ra, int rb, int rc, const Geom &g)
+{
+    const int lane = lane_id(), NW = g.NW, W = g.W;
+    const ColMasks cm = col_masks(lane < NW ? lane : 0, g);
+    const uint64_t pw = lane < NW ? pass[lane] : 0ull;
+    uint64_t cw = (lane == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
+    Reach3 out{cw, cw, cw};
+    const int rmax = (ra < 0 || rb < 0 || rc < 0) ? INT32_MAX : max(ra, max(rb, rc));
+    for (int r = 1; r <= rmax; ++r) {
+        const uint64_t prev = shfl64(cw, lane - 1), next = shfl64(cw, lane + 1);
+        const uint64_t pv = lane > 0 ? prev : 0ull, nx = lane < NW - 1 ? next : 0ull;
+        uint64_t n = cw;
+        n |= ((cw << 1) | (pv >> 63)) & ~cm.col0;
+        n |= ((cw >> 1) | (nx << 63)) & ~cm.colL;
+        n |= (cw << W) | (pv >> (64 - W));
+        n |= (cw >> W) | (nx << (64 - W));
+        n &= pw;
+        const bool changed = ballot(n != cw) != 0ull;
+        cw = n;
+        if (ra < 0 || r <= ra) out.a = cw;
+        if (rb < 0 || r <= rb) out.b = cw;
+        if (rc < 0 || r <= rc) out.c = cw;
+        if (!changed) break;
+    }
+    return out;
+}
+
+// The official rules after G1/G2 (reading R18): each further general among
+// the cells whose BFS distance to every earlier general lies in
+// [dmin, dmax], the castle count, a castle within the radius of every
+// general that has none, the rest anywhere.  `j` is the next draw index.
+// Returns false when this attempt has to be abandoned.
+__device__ bool mapgen_official(const Lds &L, const Geom &g, const GenParamsDev &prm, uint64_t seed,
+                                uint64_t env_id, uint32_t episode, int attempt, uint32_t &j, int *gp)
+{
+    const int lane = lane_id(), NW = g.NW, HW = g.HW;
+    const uint64_t *pass = L.gbm;
+    uint64_t *cand = L.gbm + 32;
+    const int lo_r = prm.dmin - 1;                       // cells within dmin-1 are too close
+    const int hi_r = prm.dmax > 0 ? prm.dmax : -1;
+    uint64_t acc = lane < NW ? pass[lane] : 0ull;        // word `lane` of the candidate set
+    uint64_t gens = 0ull;                                // word `lane` of the general cells
+    for (int i = 0;; ++i) {
+        const int gi = gp[i];
+        if (lane == (gi >> 6)) gens |= 1ull << (gi & 63);
+        if (i == g.P - 1) break;
+        const Reach3 r = bfs_reach(pass, gi, lo_r < 0 ? 0 : lo_r, hi_r, 0, g);
+        acc &= r.b & (lo_r < 0 ? ~0ull : ~r.a);
+        acc &= ~gens;
+        if (lane < NW) cand[lane] = acc;
+        const uint32_t n = (uint32_t)readfirst((int)wave_sum_u32(lane < NW ? (uint32_t)__popcll(acc) : 0u));
+        wave_sync();
+        if (n == 0) return false;
+        const int gn = bm_select(cand, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), n));
+        if (lane == 0) { gp[i + 1] = gn; L.type[gn] = GENERAL; }
+        wave_sync();
+    }
+    const int ncas = prm.cmin + (int)pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++),
+                                          (uint32_t)(prm.cmax - prm.cmin + 1));
+    uint64_t cas = 0ull;                                 // word `lane` of the castle cells
+    int placed = 0;
+    for (int i = 0; i < g.P; ++i) {
+        const Reach3 r = bfs_reach(pass, gp[i], prm.radius, 0, 0, g);
+        if (ballot((r.a & cas) != 0ull) != 0ull) continue;
+        const uint64_t c_w = lane < NW ? (r.a & pass[lane] & ~gens & ~cas) : 0ull;
+        if (lane < NW) cand[lane] = c_w;
+        const uint32_t n = (uint32_t)readfirst((int)wave_sum_u32((uint32_t)__popcll(c_w)));
+        wave_sync();
+        if (n == 0) return false;
+        const int c = bm_select(cand, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), n));
+        const int32_t a = prm.amin + (int32_t)pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++),
+                                                   (uint32_t)(prm.amax - prm.amin + 1));
+        if (lane == 0) { L.type[c] = CASTLE; L.army[c] = a; }
+        if (lane == (c >> 6)) cas |= 1ull << (c & 63);
+        ++placed;
+        wave_sync();
+    }
+    for (int t = placed; t < ncas; ++t) {
+        uint32_t n = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int c = w * 64 + lane;
+            const uint64_t m = ballot(c < HW && L.type[c] == PLAIN);
+            if (lane == 0) cand[w] = m;
+            n += (uint32_t)__popcll(m);
+        }
+        wave_sync();
+        if (n == 0) break;
+        const int c = bm_select(cand, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), n));
+        const int32_t a = prm.amin + (int32_t)pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++),
+                                                   (uint32_t)(prm.amax - prm.amin + 1));
+        if (lane == 0) { L.type[c] = CASTLE; L.army[c] = a; }
+        wave_sync();
+    }
+    return true;
+}
+
+// Section IV-A generator family (reading R14; the official rules, R18).  Executed by the whole wave
 // with uniform control flow; every random choice is a Philox draw indexed
 // exactly as the generator's draw order defines.  Leaves the grid in LDS and
 // the scalars in `s`.
@@ -100,6 +203,11 @@ __device__ void mapgen_wave(const Lds &L, const Geom &g, const GenParamsDev &prm
         // G2: first general over the non-mountain cells in row-major order
         const int g0 = bm_select(pass, NW, pick(draw32(seed, DOM_MAPGEN, env_id, episode, attempt, j++), K));
         if (lane == 0) { gp[0] = g0; L.type[g0] = GENERAL; }
+        if (prm.generator == 1) {
+            wave_sync();
+            placed = mapgen_official(L, g, prm, seed, env_id, episode, attempt, j, gp);
+            continue;
+        }
         // G3: 4-connected component of gp[0] (bitmap flood fill to a fixpoint)
         {
             const ColMasks cm = col_masks(lane < NW ? lane : 0, g);

@@ -551,7 +551,9 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
         while (!failure) {
             next += std::chrono::nanoseconds((int64_t)(h_gaps_us[(size_t)c * gaps_per_client + (k % gaps_per_client)] * 1000.0));
             ++k;
-            if (next >= t_end) break;
+            // the window ends by the arrival clock or, with zero gaps (back to
+            // back closed-loop requests), by the wall clock
+            if (next >= t_end || Clock::now() >= t_end) break;
             std::this_thread::sleep_until(next);
             ClientGroup &x = groups[(size_t)gi];
             gi = (gi + 1) % (int32_t)groups.size();

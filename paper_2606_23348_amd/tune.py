@@ -48,8 +48,9 @@ def _run_from_reset(pool: Pool, actor_seed: int, steps: int, stream):
 
 def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: int = 10, warmup: int = 2,
          verify_steps: int = 3, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
-         cands: list | None = None):
-    """Returns (best tuning dict, {candidate: mean step microseconds or None})."""
+         cands: list | None = None, progress=None):
+    """Returns (best tuning dict, {candidate: mean step microseconds or None}).
+    progress: optional callable taking a one-line message per candidate."""
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     sig = signature(specs)
@@ -87,6 +88,8 @@ def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: in
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / steps
         table[name] = us
+        if progress is not None:
+            progress(f"tune {name}: {us:.1f} us")
         if us < best_us:
             best, best_us = c, us
     if cache_path:

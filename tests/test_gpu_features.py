@@ -1,5 +1,5 @@
-"""Parity of the 38-channel features (gen_features, Appendix A) with the CPU
-oracle, through the C ABI.
+"""Parity of the 38-channel features (gen_features, Appendix A) and the two
+temporal tokens (Section V-A) with the CPU oracle, through the C ABI.
 
 Both sides step their own copy of the game with the same seeds (state parity
 itself is covered by test_gpu_parity) and record features after the reset
@@ -8,7 +8,8 @@ arithmetic: every channel is an exact integer, a 0/1 mask or a value computed
 in double and rounded once to float32 (15, 22, 23: a division, correctly
 rounded on both sides), so all must match bit for bit -- except channel 21,
 log1p in double, where the device and host math libraries may differ in the
-last double bit and so, rarely, by one float32 ulp after rounding.
+last double bit and so, rarely, by one float32 ulp after rounding.  The
+tokens are integers converted to float32: bit-exact.
 """
 import numpy as np
 import pytest
@@ -56,15 +57,17 @@ def run_case(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, record_every=1
     n_done = 0
     for t in range(steps + 1):
         if t % record_every == 0:
-            b.features()
+            b.features(tokens=True)
             torch.cuda.synchronize()
-            want = oracle.features(cfg, ost, mem)
+            want, wtok = oracle.features(cfg, ost, mem, tokens=True)
             where = f"{H}x{W} mode {mode} P {P} turn-step {t}"
             assert_features_equal(b.feat.cpu().numpy(), want, where)
+            assert np.array_equal(b.tokens.cpu().numpy(), wtok), where + " tokens"
             if t in repeat_at:                      # a second call on the same state changes nothing
-                b.features()
+                b.features(tokens=True)
                 torch.cuda.synchronize()
                 assert_features_equal(b.feat.cpu().numpy(), want, where + " (repeated)")
+                assert np.array_equal(b.tokens.cpu().numpy(), wtok), where + " tokens (repeated)"
         if t == steps:
             break
         b.step_sample(actor_seed, t + 1)
@@ -107,6 +110,31 @@ def test_features_many_episodes(gen):
     assert n > 30
 
 
+def test_tokens_window_past_512_turns(gen):
+    """Long 1v1 games (auto-reset off): the 512-turn scoreboard window wraps
+    its ring; every turn recorded twice; tokens checked on the way."""
+    import torch
+    prm = prm_for(8, 8, min_general_dist=6, auto_reset=0)
+    H = W = 8
+    b = gen.Batch(6, H, W, 0, gen.make_params(0, 2, **prm), seed=13)
+    cfg = oracle.Config(H=H, W=W, mode=0, P=2, seed=13, env_base=0, **prm)
+    ost, _ = oracle.reset(cfg, 6)
+    mem = oracle.feature_memory(6)
+    b.sample(14, 0)
+    for t in range(700):
+        b.features()
+        b.features(tokens=True)
+        oracle.features(cfg, ost, mem)
+        want, wtok = oracle.features(cfg, ost, mem, tokens=True)
+        if t in (0, 1, 300, 511, 512, 513, 650, 699):
+            torch.cuda.synchronize()
+            assert np.array_equal(b.tokens.cpu().numpy(), wtok), f"tokens at step {t}"
+            assert_features_equal(b.feat.cpu().numpy(), want, f"features at step {t}")
+        b.step_sample(14, t + 1)
+        oracle.step(cfg, ost, oracle.sample(cfg, ost, 14, t))
+    assert (ost["turn"] >= 600).any()
+
+
 def test_features_full_size_sampled(gen):
     """The 65,536-env 1v1 24x24 batch: features of every env for the first
     steps agree in their cheap invariants; a strided env subset is compared
@@ -125,11 +153,13 @@ def test_features_full_size_sampled(gen):
     idx = torch.as_tensor(ids, device="cuda")
     b.sample(wl.actor_seed, 0)
     for t in range(steps + 1):
-        b.features()
+        b.features(tokens=True)
         sub = b.feat.index_select(0, idx).cpu().numpy()
+        tsub = b.tokens.index_select(0, idx).cpu().numpy()
         for i, e in enumerate(ids):
-            want = oracle.features(cfgs[int(e)], osts[int(e)], mems[int(e)])
+            want, wtok = oracle.features(cfgs[int(e)], osts[int(e)], mems[int(e)], tokens=True)
             assert_features_equal(sub[i:i + 1], want, f"c2 env {e} step {t}")
+            assert np.array_equal(tsub[i:i + 1], wtok), f"c2 env {e} step {t} tokens"
         if t == steps:
             break
         b.step_sample(wl.actor_seed, t + 1)
@@ -144,3 +174,38 @@ def test_features_full_size_sampled(gen):
     assert torch.equal(own.sum(dim=(2, 3)), f[:, :, 16, 0, 0])
     turn = torch.as_tensor(b.get_state()["turn"], device="cuda").float()
     assert torch.equal(f[:, 0, 14, 0, 0], turn)
+
+
+@pytest.mark.parametrize("generator", [0, 1])
+def test_rollout_matches_oracle(gen, generator):
+    """gen_rollout = features, random actor, step, T times; compared with the
+    oracle doing the same, step by step, on every buffer slice."""
+    import torch
+    H = W = 10
+    E, T, seed, actor = 12, 40, 77, 78
+    prm = prm_for(H, W, generator=generator, min_general_dist=5 if generator else 4, castle_radius=6)
+    b = gen.Batch(E, H, W, 0, gen.make_params(0, 2, **prm), seed=seed)
+    cfg = oracle.Config(H=H, W=W, mode=0, P=2, seed=seed, env_base=0, **prm)
+    ost, _ = oracle.reset(cfg, E)
+    mem = oracle.feature_memory(E)
+    out = b.rollout(T, actor, 0, tokens=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    for t in range(T):
+        want, wtok = oracle.features(cfg, ost, mem, tokens=True)
+        assert_features_equal(got["feat"][t], want, f"rollout t={t}")
+        assert np.array_equal(got["tokens"][t], wtok), f"rollout tokens t={t}"
+        act = oracle.sample(cfg, ost, actor, t)
+        assert np.array_equal(got["actions"][t], act), f"rollout actions t={t}"
+        r, d = oracle.step(cfg, ost, act)
+        assert np.array_equal(got["rewards"][t], r) and np.array_equal(got["dones"][t], d), f"rollout t={t}"
+    st = b.get_state()
+    for k in ("owner", "army", "type", "turn", "episode"):
+        assert np.array_equal(st[k], ost[k]), k
+    # a second rollout continues the same trajectory and memory
+    out2 = b.rollout(5, actor, T, tokens=False, out={k: v[:5] for k, v in out.items() if k != "tokens"})
+    torch.cuda.synchronize()
+    for t in range(5):
+        want = oracle.features(cfg, ost, mem)
+        assert_features_equal(out2["feat"][t].cpu().numpy(), want, f"second rollout t={t}")
+        oracle.step(cfg, ost, oracle.sample(cfg, ost, actor, T + t))

@@ -325,3 +325,34 @@ def test_full_size_workload(gen, name, steps_all, steps_sub):
             assert np.array_equal(grew[e], r[0]) and gdone[e] == d[0], where
             assert_state_equal({k: v[j:j + 1] for k, v in gst.items()}, s, where)
             assert_obs_equal(gobs[j:j + 1], oracle.observe(c, s), where)
+
+
+# ------------------------------------------------------------------ official generator (reading R18)
+@pytest.mark.parametrize("H,W,mode,P,E,dmin,dmax,radius", [
+    (23, 23, 0, 2, 64, 17, 0, 6),      # the official 1v1 rules
+    (16, 16, 0, 2, 64, 1, 4, 6),       # a curriculum stage: spawn distance capped at 4
+    (20, 20, 1, 4, 32, 6, 0, 6),       # 2v2
+    (18, 13, 2, 5, 32, 5, 9, 5),       # FFA-5 with both bounds
+    (5, 5, 0, 2, 64, 3, 0, 4),         # small: some envs need several attempts
+])
+def test_official_reset_matches_oracle(gen, H, W, mode, P, E, dmin, dmax, radius):
+    import torch
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(9, H * W // 8),
+               cities_max=min(11, H * W // 6), min_general_dist=dmin, auto_reset=1, generator=1,
+               max_general_dist=dmax, castle_radius=radius)
+    b = gen.Batch(E, H, W, mode, gparams(gen, mode, P, prm), seed=H * 7 + W)
+    cfg = ocfg(H, W, mode, P, H * 7 + W, **prm)
+    ost, att = oracle.reset(cfg, E)
+    torch.cuda.synchronize()
+    assert_state_equal(b.get_state(), ost, f"official reset {H}x{W}")
+    assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), f"official reset obs {H}x{W}")
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_official_trajectory_with_regeneration(gen, fused):
+    """Small official maps end often: every auto-reset runs the official
+    generator inside the step kernel."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=2, min_general_dist=3,
+               auto_reset=1, generator=1, max_general_dist=0, castle_radius=4)
+    n = run_parity(gen, 5, 5, 0, 2, 64, 300, seed=33, actor_seed=34, prm=prm, fused=fused)
+    assert n > 10

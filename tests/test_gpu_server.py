@@ -154,3 +154,18 @@ def test_server_native_clients(gen):
     assert 0 < rep["lat_p50_us"] <= rep["lat_p99_us"]
     assert srv.report()["groups_open"] == 0
     srv.close_server()
+
+
+def test_server_back_to_back_clients_end_on_time(gen):
+    """All-zero arrival gaps mean back-to-back closed-loop requests; the
+    measured window still ends after duration_s."""
+    import time
+    srv = gen.Server(256 << 20, n_launch_streams=2)
+    sizes = np.full(8, 64)
+    specs = workloads.mixed_specs(int(sizes.sum()), 9)
+    t0 = time.perf_counter()
+    rep = srv.drive(sizes, specs, seed=9, actor_seed=10, gaps_us=np.zeros((8, 1)), duration_s=0.3,
+                    steps_per_group=0, common=common(gen))
+    assert time.perf_counter() - t0 < 30
+    assert rep["requests"] > 8 and 0.3 <= rep["wall_s"] < 5
+    srv.close_server()
