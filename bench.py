@@ -275,7 +275,8 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
             "per_bucket_plain": {"buckets": int(len(uniq)), "frames_per_s": wl.n_envs / bucket_s,
                                  "ms_per_step": bucket_s * 1e3},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": bpf}}
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": bpf,
+                         "traffic": traffic_for(wl.name, wl.n_envs)}}
 
 
 def run_served_c2(gen, torch, duration_s: float) -> dict:

@@ -396,13 +396,22 @@ int gen_server_wait(gen_server *srv, uint64_t ticket, int64_t timeout_us);
 int gen_server_close(gen_server *srv, uint64_t group);
 int gen_server_report(gen_server *srv, gen_server_stats *out, int32_t reset);
 
+/* Batching window: a launch starts when every open group is either on the
+ * GPU or has a request waiting, or when the waiting requests hold
+ * min_batch_envs envs (0 = a quarter of the envs of the open groups), or
+ * when the oldest of them has waited max_wait_us (default 100).  Larger
+ * batches spread the per-launch host cost over more envs; max_wait_us
+ * bounds the latency it adds. */
+int gen_server_set_batching(gen_server *srv, int64_t min_batch_envs, int64_t max_wait_us);
+
 /* Synthetic clients for measuring the server (load generator, not part of
- * the step): n_clients threads, each owning groups_per_client groups opened
- * from h_specs (env specs of all groups back to back, group g has
- * h_group_envs[g] envs), issuing closed-loop requests -- a group's next
- * request only after its previous one completed -- paced by the arrival gaps
- * h_gaps_us[client][k] (microseconds; all zero = back to back), until
- * duration_us has passed.  A group that reached steps_per_group steps is
+ * the step): n_clients logical clients (run as state machines by up to 8
+ * threads), each owning groups_per_client groups opened from h_specs (env
+ * specs of all groups back to back, group g has h_group_envs[g] envs), each
+ * issuing, when its arrival timer fires, one request for its next group in
+ * turn once that group's previous request has completed (closed loop per
+ * group); the timer follows the arrival gaps h_gaps_us[client][k]
+ * (microseconds; all zero = back to back) until duration_us has passed.  A group that reached steps_per_group steps is
  * closed and reopened (same specs, next env ids) when steps_per_group > 0.
  * Returns the stats of the run. */
 int gen_server_drive(gen_server *srv, int32_t n_clients, int32_t groups_per_client, const int32_t *h_group_envs,

@@ -138,6 +138,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_server_wait.argtypes = [vp, u64, ctypes.c_int64]
     L.gen_server_close.argtypes = [vp, u64]
     L.gen_server_report.argtypes = [vp, P(gen_server_stats), i32]
+    L.gen_server_set_batching.argtypes = [vp, ctypes.c_int64, ctypes.c_int64]
     L.gen_server_drive.argtypes = [vp, i32, i32, vp, vp, P(gen_params), u64, u64, vp, i32, ctypes.c_int64, i32,
                                    P(gen_server_stats)]
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
@@ -146,7 +147,7 @@ def load_library(path: str) -> ctypes.CDLL:
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
               "gen_pool_get_env", "gen_server_create", "gen_server_destroy", "gen_server_open",
               "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
-              "gen_server_report", "gen_server_drive"):
+              "gen_server_report", "gen_server_set_batching", "gen_server_drive"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -568,6 +569,9 @@ class Server:
 
     def close(self, group: int):
         _check(lib().gen_server_close(self.handle, group))
+
+    def set_batching(self, min_batch_envs: int = 0, max_wait_us: int = 100):
+        _check(lib().gen_server_set_batching(self.handle, min_batch_envs, max_wait_us))
 
     def report(self, reset: bool = False) -> dict:
         st = gen_server_stats()

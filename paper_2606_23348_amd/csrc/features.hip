@@ -8,9 +8,10 @@
 // player), so the kernel keeps every store coalesced: lane i of a round
 // handles cell 64r + i, and each of the 38 channel stores of a player is one
 // contiguous 256-byte wave store, nontemporal.  The state sits in LDS only
-// for the ballots and the team-vision dilation.  The delta stacks walk the
-// ring one frame at a time for all players, so only two running values per
-// player stay live.
+// for the ballots and the team-vision dilation.  A cell's 7 earlier frames
+// are loaded from the ring before its 24 instantaneous channels are written,
+// so their latency hides behind those stores; the delta stacks then walk the
+// frames for all players with two running values per player.
 #include "internal.hpp"
 
 namespace gen {
@@ -156,6 +157,17 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         uint32_t vb = 0;
         for (int p = 0; p < P; ++p) vb |= (uint32_t)((vis[p * 16 + w] >> b) & 1ull) << p;
 
+        int hq[kHist];
+        uint32_t hqv[kHist];
+        int32_t hqa[kHist];
+#pragma unroll
+        for (int k = 0; k < kHist; ++k) {
+            const int sl = (t - k - 1) & 7;
+            const bool have = (hv >> (k + 1)) & 1u;
+            hq[k] = have ? (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fowner + sl * S, 0) : -1;
+            hqv[k] = have ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fvis + sl * S, 0) : 0u;
+            hqa[k] = have ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * c, (int)fb.farmy + 4 * sl * S, 0) : 0;
+        }
         __builtin_amdgcn_raw_buffer_store_b8((uint8_t)o, rm, c, (int)fb.fowner + slot * S, kNT);
         __builtin_amdgcn_raw_buffer_store_b8((uint8_t)vb, rm, c, (int)fb.fvis + slot * S, kNT);
         __builtin_amdgcn_raw_buffer_store_b32((uint32_t)av, rm, 4 * c, (int)fb.farmy + 4 * slot * S, kNT);
@@ -227,13 +239,11 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         }
 
         // delta stacks: frame t-k-1 from the ring (absent: empty board)
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < kHist; ++k) {
-            const int sl = (t - k - 1) & 7;
-            const bool have = (hv >> (k + 1)) & 1u;
-            const int q = have ? (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fowner + sl * S, 0) : -1;
-            const uint32_t qv = have ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rm, c, (int)fb.fvis + sl * S, 0) : 0u;
-            const int32_t qa = have ? (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * c, (int)fb.farmy + 4 * sl * S, 0) : 0;
+            const int q = hq[k];
+            const uint32_t qv = hqv[k];
+            const int32_t qa = hqa[k];
 #pragma unroll
             for (int p = 0; p < kMaxP; ++p) {
                 if (p >= P) break;

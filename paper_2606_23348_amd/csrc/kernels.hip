@@ -27,7 +27,7 @@ struct Lds {
 
 uint32_t lds_bytes_for(int S, int P)
 {
-    const int code = (P * S + 16 <= 4 * S) ? 0 : P * S + 16;   // see carve()
+    const int code = (P <= 4) ? 0 : P * S + 16;   // see carve()
     return (uint32_t)(4 * S + S + S + (S + 16) + code + 8 * 16 * (2 * P + 3) + 32);
 }
 
@@ -41,8 +41,10 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
     L.armyc = smem + o; o += g.S + 16;
     // The code planes are written only after the last read of the army row
     // (the state store), so when they fit they reuse its space: less LDS per
-    // env, more waves per CU.
-    if (g.P * g.S + 16 <= 4 * g.S) {
+    // env, more waves per CU.  Up to 4 players they fit (P*S <= 4S); the
+    // 16-byte read slack past the last plane then falls on the owner row,
+    // whose bytes the funnel shifts discard.
+    if (g.P <= 4) {
         L.code = smem;
     } else {
         L.code = smem + o; o += g.P * g.S + 16;
@@ -481,7 +483,9 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
 
 // ---------------------------------------------------------------- fused env kernel
 enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
-enum { OBS_A16 = 0, OBS_A4 = 1, OBS_A1C16 = 2, OBS_A1C8 = 3, OBS_RUNTIME = -1 };
+// Observation writers: planes of a multiple of 4 cells (dword aligned) or any
+// other size; OBS_RUNTIME decides per env from the geometry (mixed shapes).
+enum { OBS_QUAD = 0, OBS_STREAM = 1, OBS_RUNTIME = -1 };
 
 __device__ __forceinline__ uint32_t vismask(uint32_t code4)
 {
@@ -512,69 +516,6 @@ __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32
     const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
     const uint32_t cd = L.code[p * g.S + c];
     return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
-}
-
-// Four obs bytes at byte offset b (b % 4 == 0) of an env block whose planes
-// are 4-byte aligned (H*W % 4 == 0): the dword lies inside one plane.
-__device__ __forceinline__ uint32_t obs_dword_a4(const Lds &L, const Geom &g, uint32_t b)
-{
-    const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-    const uint32_t cd = *reinterpret_cast<const uint32_t *>(L.code + p * g.S + c);
-    if (ch < 7) return (cd >> ch) & 0x01010101u;
-    return *reinterpret_cast<const uint32_t *>(L.armyc + c) & vismask(cd);
-}
-
-// Unaligned run of N/4 dwords from an LDS byte array starting at byte o:
-// N/4 + 1 aligned dword reads and a byte funnel shift per output dword.
-template <int N, bool ALIGN4>
-__device__ __forceinline__ void lds_run(const uint8_t *base, uint32_t o, uint32_t (&out)[N / 4])
-{
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(base) + (o >> 2);
-    if (ALIGN4) {
-#pragma unroll
-        for (int i = 0; i < N / 4; ++i) out[i] = w[i];
-    } else {
-        uint32_t raw[N / 4 + 1];
-#pragma unroll
-        for (int i = 0; i <= N / 4; ++i) raw[i] = w[i];
-#pragma unroll
-        for (int i = 0; i < N / 4; ++i) out[i] = __builtin_amdgcn_alignbyte(raw[i + 1], raw[i], o & 3);
-    }
-}
-
-// N obs bytes (N = 8 or 16) at byte offset b (b % N == 0) of an env block.
-// The chunk index is decoded once; a chunk inside one plane is N consecutive
-// cells of one (player, channel); a chunk across a plane boundary falls back
-// to dwords (4-byte aligned planes) or single bytes.
-template <int N, bool ALIGN4>
-__device__ __forceinline__ void obs_chunk(const Lds &L, const Geom &g, uint32_t b, uint32_t (&out)[N / 4])
-{
-    const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-    if (c + N <= (uint32_t)g.HW) {
-        uint32_t cd[N / 4];
-        lds_run<N, ALIGN4>(L.code, p * g.S + c, cd);
-        if (ch < 7) {
-#pragma unroll
-            for (int i = 0; i < N / 4; ++i) out[i] = (cd[i] >> ch) & 0x01010101u;
-        } else {
-            uint32_t ac[N / 4];
-            lds_run<N, ALIGN4>(L.armyc, c, ac);
-#pragma unroll
-            for (int i = 0; i < N / 4; ++i) out[i] = ac[i] & vismask(cd[i]);
-        }
-    } else if (ALIGN4) {
-#pragma unroll
-        for (int i = 0; i < N / 4; ++i) out[i] = obs_dword_a4(L, g, b + 4 * i);
-    } else {
-        // rare (a chunk across a plane boundary): byte by byte, kept rolled
-#pragma unroll
-        for (int i = 0; i < N / 4; ++i) {
-            uint32_t v = 0;
-#pragma nounroll
-            for (int j = 0; j < 4; ++j) v |= obs_byte(L, g, b + 4 * i + j) << (8 * j);
-            out[i] = v;
-        }
-    }
 }
 
 // Per-env inputs and outputs of one step (pointers into this env's rows).
@@ -751,7 +692,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     // planes (4-byte stores, 256 contiguous bytes per wave store).  Other
     // shapes stage the code bytes in LDS for the chunk writers below.
     const bool quad_obs =
-        (OBSV == OBS_A16 || OBSV == OBS_A4) || (OBSV == OBS_RUNTIME && (g.HW & 3) == 0);
+        OBSV == OBS_QUAD || (OBSV == OBS_RUNTIME && (g.HW & 3) == 0);
     if (quad_obs) {
         if (io.obs != nullptr) {
             const int nq = g.HW >> 2;
@@ -779,68 +720,32 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     }
     wave_sync();
 
-    // ---- observation stream for the other plane sizes: 16- or 8-byte stores
+    // ---- observation stream for the other plane sizes: one output dword per
+    // lane and round (consecutive lanes read consecutive LDS dwords: no bank
+    // conflicts), its 4 code bytes funnel-shifted out of two aligned dwords
     if (io.obs != nullptr && !quad_obs) {
         const uint32_t B = (uint32_t)(g.P * 8 * g.HW);
-        uint8_t *ob = io.obs;
-        if (OBSV == OBS_RUNTIME) {
-            // mixed shapes in one launch: one generic writer for every plane alignment
-            if ((B & 15u) == 0) {
-                for (uint32_t k = lane; k < (B >> 4); k += kWave) {
-                    const uint32_t b = k << 4;
-                    uint32_t o[4];
-                    obs_chunk<16, false>(L, g, b, o);
-                    st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
+        uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
+        for (uint32_t k = lane; k < (B >> 2); k += kWave) {
+            const uint32_t b = k << 2;
+            const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
+            uint32_t v;
+            if (c + 4 <= (uint32_t)g.HW) {
+                const uint32_t *cw = reinterpret_cast<const uint32_t *>(L.code + p * g.S) + (c >> 2);
+                const uint32_t cd = __builtin_amdgcn_alignbyte(cw[1], cw[0], c & 3);
+                if (ch < 7) {
+                    v = (cd >> ch) & 0x01010101u;
+                } else {
+                    const uint32_t *aw = reinterpret_cast<const uint32_t *>(L.armyc) + (c >> 2);
+                    v = __builtin_amdgcn_alignbyte(aw[1], aw[0], c & 3) & vismask(cd);
                 }
             } else {
-                for (uint32_t k = lane; k < (B >> 3); k += kWave) {
-                    const uint32_t b = k << 3;
-                    uint32_t o[2];
-                    obs_chunk<8, false>(L, g, b, o);
-                    st_nt(reinterpret_cast<uint2 *>(ob + b), make_uint2(o[0], o[1]));
-                }
+                // a dword across a plane boundary (one per plane at most)
+                v = 0;
+#pragma nounroll
+                for (int j = 0; j < 4; ++j) v |= obs_byte(L, g, b + j) << (8 * j);
             }
-        } else if (OBSV == OBS_A16) {
-            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
-                const uint32_t b = k << 4;
-                const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-                const uint4 cd = *reinterpret_cast<const uint4 *>(L.code + p * g.S + c);
-                uint4 out;
-                if (ch < 7) {
-                    out.x = (cd.x >> ch) & 0x01010101u;
-                    out.y = (cd.y >> ch) & 0x01010101u;
-                    out.z = (cd.z >> ch) & 0x01010101u;
-                    out.w = (cd.w >> ch) & 0x01010101u;
-                } else {
-                    const uint4 ac = *reinterpret_cast<const uint4 *>(L.armyc + c);
-                    out.x = ac.x & vismask(cd.x);
-                    out.y = ac.y & vismask(cd.y);
-                    out.z = ac.z & vismask(cd.z);
-                    out.w = ac.w & vismask(cd.w);
-                }
-                st_nt(reinterpret_cast<uint4 *>(ob + b), out);
-            }
-        } else if (OBSV == OBS_A4) {
-            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
-                const uint32_t b = k << 4;
-                uint32_t o[4];
-                obs_chunk<16, true>(L, g, b, o);
-                st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
-            }
-        } else if (OBSV == OBS_A1C16) {
-            for (uint32_t k = lane; k < (B >> 4); k += kWave) {
-                const uint32_t b = k << 4;
-                uint32_t o[4];
-                obs_chunk<16, false>(L, g, b, o);
-                st_nt(reinterpret_cast<uint4 *>(ob + b), make_uint4(o[0], o[1], o[2], o[3]));
-            }
-        } else {
-            for (uint32_t k = lane; k < (B >> 3); k += kWave) {
-                const uint32_t b = k << 3;
-                uint32_t o[2];
-                obs_chunk<8, false>(L, g, b, o);
-                st_nt(reinterpret_cast<uint2 *>(ob + b), make_uint2(o[0], o[1]));
-            }
+            st_nt(ob + k, v);
         }
     }
 
@@ -995,9 +900,8 @@ uint32_t lds_bytes(const Geom &g) { return lds_bytes_for(g.S, g.P); }
 
 int obs_variant(int HW, int P)
 {
-    if (HW % 16 == 0) return OBS_A16;
-    if (HW % 4 == 0) return OBS_A4;
-    return ((P * 8 * HW) % 16 == 0) ? OBS_A1C16 : OBS_A1C8;
+    (void)P;
+    return HW % 4 == 0 ? OBS_QUAD : OBS_STREAM;
 }
 
 static int obs_variant(const Geom &g) { return obs_variant(g.HW, g.P); }
@@ -1008,10 +912,8 @@ static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
     const dim3 grid((unsigned)n_envs), block(kWave);
     const uint32_t lds = lds_bytes(a.g);
     switch (obs_variant(a.g)) {
-    case OBS_A16: hipLaunchKernelGGL((k_env<KIND, OBS_A16, SB, ACT>), grid, block, lds, stream, a); break;
-    case OBS_A4: hipLaunchKernelGGL((k_env<KIND, OBS_A4, SB, ACT>), grid, block, lds, stream, a); break;
-    case OBS_A1C16: hipLaunchKernelGGL((k_env<KIND, OBS_A1C16, SB, ACT>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_env<KIND, OBS_A1C8, SB, ACT>), grid, block, lds, stream, a); break;
+    case OBS_QUAD: hipLaunchKernelGGL((k_env<KIND, OBS_QUAD, SB, ACT>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_env<KIND, OBS_STREAM, SB, ACT>), grid, block, lds, stream, a); break;
     }
     return hipGetLastError();
 }

@@ -85,6 +85,7 @@ struct Group {
     bool closing = false;
     int waiters = 0;            // clients blocked on cv (close waits for them to leave)
     std::condition_variable cv; // completion of this group's tickets
+    std::atomic<uint64_t> completed{0};   // requests finished (lock-free progress check)
 };
 
 struct Ticket {
@@ -111,6 +112,10 @@ struct gen_server {
     int device = 0;
     uint32_t max_batch_envs = 0;
     uint32_t max_reqs = 0;
+    // batching window while another launch is in flight (gen_server_set_batching)
+    int64_t min_batch_envs = 0;                        // 0: a quarter of the open envs
+    int64_t max_wait_us = 100;
+    int64_t open_envs = 0;                             // envs of the open groups
     Arena alloc;
     std::mutex mu;
     std::condition_variable cv_sched;
@@ -147,6 +152,7 @@ void complete_slot(gen_server &s, Slot &sl, int status)
                 s.st_requests += 1;
                 s.st_frames += (uint64_t)g->second->n_envs;
             }
+            g->second->completed.fetch_add(1, std::memory_order_release);
             g->second->cv.notify_all();
         }
     }
@@ -204,7 +210,29 @@ void scheduler(gen_server *sp)
         Slot *free_slot = nullptr;
         for (auto &sl : s.slots)
             if (!sl.busy) { free_slot = &sl; break; }
-        if (free_slot && !s.queue.empty() && s.error.empty()) {
+        bool launch_now = free_slot && !s.queue.empty() && s.error.empty();
+        if (launch_now) {
+            // Launch when no other open group can still join (every group is
+            // either on the GPU or has a request waiting), when the ready
+            // requests reach the batch size, or when the oldest has waited
+            // max_wait_us.  Closed-loop clients then settle into cohorts that
+            // alternate between the GPU and the queue.
+            int64_t ready = 0, oldest = INT64_MAX, inflight = 0;
+            for (uint64_t tk : s.queue) {
+                auto t = s.tickets.find(tk);
+                if (t == s.tickets.end() || t->second.status != 1) continue;
+                auto gi = s.groups.find(t->second.group);
+                if (gi == s.groups.end() || gi->second->busy) continue;
+                ready += gi->second->n_envs;
+                oldest = std::min(oldest, t->second.t_submit);
+            }
+            for (const auto &x : s.slots)
+                if (x.busy) inflight += (int64_t)x.envs;
+            const int64_t idle = s.open_envs - inflight - ready;
+            const int64_t want = s.min_batch_envs > 0 ? s.min_batch_envs : std::max<int64_t>(1, s.open_envs / 4);
+            launch_now = ready > 0 && (idle <= 0 || ready >= want || now_ns() - oldest >= s.max_wait_us * 1000);
+        }
+        if (launch_now) {
             Slot &sl = *free_slot;
             uint32_t n_req = 0, wg = 0, lds = 0;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
@@ -246,9 +274,18 @@ void scheduler(gen_server *sp)
             }
         }
         if (!progressed) {
+            // With work pending (a launch on the GPU or requests in the queue)
+            // keep polling: a timed sleep overshoots by tens of microseconds,
+            // which would add to every request's latency.  Fully idle: block
+            // until a client submits.
             const bool inflight = std::any_of(s.slots.begin(), s.slots.end(), [](const Slot &x) { return x.busy; });
-            if (inflight) s.cv_sched.wait_for(lk, std::chrono::microseconds(10));
-            else s.cv_sched.wait_for(lk, std::chrono::milliseconds(5));
+            if (inflight || !s.queue.empty()) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                s.cv_sched.wait_for(lk, std::chrono::milliseconds(5));
+            }
         }
     }
 }
@@ -365,6 +402,7 @@ int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_e
     }
     g->busy = false;
     *group = g->id;
+    s->open_envs += g->n_envs;
     s->groups[g->id] = std::move(g);
     return GEN_OK;
 }
@@ -456,7 +494,21 @@ int gen_server_close(gen_server *s, uint64_t group)
     const uint64_t o[5] = {g.off_state, g.off_obs, g.off_act, g.off_rew, g.off_done};
     for (int j = 0; j < 5; ++j) s->alloc.release(o[j], sz[j]);
     gen_pool_destroy(g.pool);
+    s->open_envs -= g.n_envs;
     s->groups.erase(it);
+    return GEN_OK;
+}
+
+int gen_server_set_batching(gen_server *s, int64_t min_batch_envs, int64_t max_wait_us)
+{
+    if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
+    if (min_batch_envs < 0 || max_wait_us < 0) return sfail(GEN_EINVAL, "min_batch_envs and max_wait_us must be >= 0");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->min_batch_envs = min_batch_envs;
+        s->max_wait_us = max_wait_us;
+    }
+    s->cv_sched.notify_one();
     return GEN_OK;
 }
 
@@ -505,7 +557,16 @@ struct ClientGroup {
     int32_t steps = 0;
     int32_t spec_begin = 0, n_envs = 0;
     uint64_t env_base = 0;
+    Group *g = nullptr;          // the server's group object (stable until closed)
+    uint64_t mark = 0;           // its completion count when the request was submitted
 };
+
+Group *group_of(gen_server *s, uint64_t id)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->groups.find(id);
+    return it == s->groups.end() ? nullptr : it->second.get();
+}
 
 }  // namespace
 
@@ -540,46 +601,64 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
         }
     }
     if (failure) return failure.load();
+    for (auto &v : cg)
+        for (auto &x : v) x.g = group_of(s, x.id);
     gen_server_stats tmp;
     gen_server_report(s, &tmp, 1);
     const auto t0 = Clock::now();
     const auto t_end = t0 + std::chrono::microseconds(duration_us);
-    auto client = [&](int32_t c) {
-        auto &groups = cg[(size_t)c];
-        auto next = t0;
-        int32_t gi = 0, k = 0;
+    auto gap = [&](int32_t c, int32_t k) {
+        return std::chrono::nanoseconds((int64_t)(h_gaps_us[(size_t)c * gaps_per_client + (k % gaps_per_client)] * 1000.0));
+    };
+    // The clients are logical: a few threads each run many of them as state
+    // machines (timer fired -> previous request of the group finished ->
+    // submit), polling completions lock-free, so the measurement is not
+    // bounded by waking one OS thread per client.
+    const int32_t n_threads = std::min<int32_t>(n_clients, 8);
+    auto worker = [&](int32_t t) {
+        struct Cl { int32_t c, gi, k; Clock::time_point next; };
+        std::vector<Cl> cl;
+        for (int32_t c = t; c < n_clients; c += n_threads) cl.push_back({c, 0, 1, t0 + gap(c, 0)});
         while (!failure) {
-            next += std::chrono::nanoseconds((int64_t)(h_gaps_us[(size_t)c * gaps_per_client + (k % gaps_per_client)] * 1000.0));
-            ++k;
-            // the window ends by the arrival clock or, with zero gaps (back to
-            // back closed-loop requests), by the wall clock
-            if (next >= t_end || Clock::now() >= t_end) break;
-            std::this_thread::sleep_until(next);
-            ClientGroup &x = groups[(size_t)gi];
-            gi = (gi + 1) % (int32_t)groups.size();
-            if (x.outstanding) {
-                const int rc = gen_server_wait(s, x.ticket, kDriveWaitUs);
-                if (rc != GEN_OK) { failure = rc; break; }
-                x.outstanding = false;
-                x.steps += 1;
+            const auto now = Clock::now();
+            if (now >= t_end) break;
+            bool progressed = false;
+            for (auto &x : cl) {
+                if (failure) break;
+                if (x.next >= t_end || now < x.next) continue;
+                ClientGroup &grp = cg[(size_t)x.c][(size_t)x.gi];
+                if (grp.outstanding) {
+                    if (grp.g->completed.load(std::memory_order_acquire) <= grp.mark) continue;
+                    const int rc = gen_server_wait(s, grp.ticket, kDriveWaitUs);
+                    if (rc != GEN_OK) { failure = rc; break; }
+                    grp.outstanding = false;
+                    grp.steps += 1;
+                }
+                if (steps_per_group > 0 && grp.steps >= steps_per_group) {
+                    if (gen_server_close(s, grp.id) != GEN_OK) { failure = GEN_EHIP; break; }
+                    grp.env_base = reopen_base.fetch_add((uint64_t)grp.n_envs);
+                    const int rc = gen_server_open(s, seed, grp.env_base, grp.n_envs, h_specs + grp.spec_begin, common,
+                                                   1, actor_seed, &grp.id);
+                    if (rc != GEN_OK) { failure = rc; break; }
+                    grp.g = group_of(s, grp.id);
+                    grp.steps = 0;
+                }
+                grp.mark = grp.g->completed.load(std::memory_order_acquire);
+                if (gen_server_submit(s, grp.id, &grp.ticket) != GEN_OK) { failure = GEN_EHIP; break; }
+                grp.outstanding = true;
+                x.gi = (x.gi + 1) % (int32_t)cg[(size_t)x.c].size();
+                x.next += gap(x.c, x.k++);
+                progressed = true;
             }
-            if (steps_per_group > 0 && x.steps >= steps_per_group) {
-                if (gen_server_close(s, x.id) != GEN_OK) { failure = GEN_EHIP; break; }
-                x.env_base = reopen_base.fetch_add((uint64_t)x.n_envs);
-                const int rc = gen_server_open(s, seed, x.env_base, x.n_envs, h_specs + x.spec_begin, common, 1,
-                                               actor_seed, &x.id);
-                if (rc != GEN_OK) { failure = rc; break; }
-                x.steps = 0;
-            }
-            if (gen_server_submit(s, x.id, &x.ticket) != GEN_OK) { failure = GEN_EHIP; break; }
-            x.outstanding = true;
+            if (!progressed) std::this_thread::yield();
         }
-        for (auto &x : groups)
-            if (x.outstanding) { gen_server_wait(s, x.ticket, kDriveWaitUs); x.outstanding = false; }
+        for (auto &x : cl)
+            for (auto &grp : cg[(size_t)x.c])
+                if (grp.outstanding) { gen_server_wait(s, grp.ticket, kDriveWaitUs); grp.outstanding = false; }
     };
     std::vector<std::thread> th;
-    th.reserve((size_t)n_clients);
-    for (int32_t c = 0; c < n_clients; ++c) th.emplace_back(client, c);
+    th.reserve((size_t)n_threads);
+    for (int32_t t = 0; t < n_threads; ++t) th.emplace_back(worker, t);
     for (auto &t : th) t.join();
     const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
     gen_server_report(s, out, 1);
