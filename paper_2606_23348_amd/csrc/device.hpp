@@ -189,6 +189,8 @@ __device__ __forceinline__ ColMasks col_masks(int w, const Geom &g)
 // Observation planes and the state are written once per step and not read
 // again by the same launch; nontemporal stores keep them from crowding the
 // caches (measured: a step at the copy ceiling instead of 20% below it).
+// Only for whole, sector-aligned runs: where two stores share a 32-byte
+// sector (unaligned observation planes) plain stores are faster.
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 

@@ -49,8 +49,13 @@ __device__ __forceinline__ float age_of(int32_t dt)
 
 }  // namespace
 
+// NT: the feature planes are whole 32-byte sectors (H*W a multiple of 8),
+// so their stores can be nontemporal; otherwise two stores share the sector
+// at each plane boundary and plain stores let the cache merge them.
+template <bool NT>
 __global__ __launch_bounds__(64) void k_features(FeatArgs a)
 {
+    constexpr int kOut = NT ? kNT : 0;        // cache policy of the feature and token stores
     extern __shared__ __align__(16) uint8_t smem[];
     const int e = blockIdx.x, lane = lane_id();
     const Geom g = a.g;
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
             }
             const int pb = p * kFeatC * HW * 4;
             auto put = [&](int ch, float x) {
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rf, 4 * c, pb + ch * HW * 4, kNT);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rf, 4 * c, pb + ch * HW * 4, kOut);
             };
             put(0, (float)(v ? av : 0));
             put(1, (float)(o == p ? av : 0));
@@ -251,9 +256,9 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
                 const int32_t own_k = q == p ? qa : 0;
                 const int32_t en_k = (((qv >> p) & 1u) && enemy_of(q, p, g.mode)) ? qa : 0;
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)(own_prev[p] - own_k)), rf, 4 * c,
-                                                      pb + (24 + k) * HW * 4, kNT);
+                                                      pb + (24 + k) * HW * 4, kOut);
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)(en_prev[p] - en_k)), rf, 4 * c,
-                                                      pb + (24 + kHist + k) * HW * 4, kNT);
+                                                      pb + (24 + kHist + k) * HW * 4, kOut);
                 own_prev[p] = own_k;
                 en_prev[p] = en_k;
             }
@@ -296,9 +301,9 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
                     ol = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (p * kTokenWindow + sl), (int)fb.tland, 0);
                 }
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)oa), rt, 4 * j,
-                                                      4 * (p * 2 * kTokenWindow), kNT);
+                                                      4 * (p * 2 * kTokenWindow), kOut);
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((float)ol), rt, 4 * j,
-                                                      4 * (p * 2 * kTokenWindow + kTokenWindow), kNT);
+                                                      4 * (p * 2 * kTokenWindow + kTokenWindow), kOut);
             }
         }
     }
@@ -314,7 +319,10 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)
 {
     const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8 + 12 * a.g.P);
-    hipLaunchKernelGGL(k_features, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
+    if (a.g.HW % 8 == 0)
+        hipLaunchKernelGGL(k_features<true>, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
+    else
+        hipLaunchKernelGGL(k_features<false>, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
     return hipGetLastError();
 }
 

@@ -11,8 +11,6 @@ namespace gen {
 // ---------------------------------------------------------------- LDS carve-up
 // Per env, S = padded cells per row (multiple of 16):
 //   army  int32 [S] | owner int8 [S] | type uint8 [S] | armyc uint8 [S] + 16
-//   code  uint8 [P*S] + 16            (per player, bits = obs channels 0..6;
-//                                      overlays the army row when it fits)
 //   obm   u64 [P][16]                 (cells owned by each player)
 //   vis   u64 [P][16]                 (visible cell bitmaps)
 //   gbm   u64 [3][16] + int32 [8]      (map generator scratch bitmaps, general cells)
@@ -21,14 +19,12 @@ struct Lds {
     int8_t *owner;
     uint8_t *type;
     uint8_t *armyc;
-    uint8_t *code;
     uint64_t *obm, *vis, *gbm;
 };
 
 uint32_t lds_bytes_for(int S, int P)
 {
-    const int code = (P <= 4) ? 0 : P * S + 16;   // see carve()
-    return (uint32_t)(4 * S + S + S + (S + 16) + code + 8 * 16 * (2 * P + 3) + 32);
+    return (uint32_t)(4 * S + S + S + (S + 16) + 8 * 16 * (2 * P + 3) + 32);
 }
 
 __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
@@ -39,16 +35,6 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
     L.owner = reinterpret_cast<int8_t *>(smem + o); o += g.S;
     L.type = smem + o; o += g.S;
     L.armyc = smem + o; o += g.S + 16;
-    // The code planes are written only after the last read of the army row
-    // (the state store), so when they fit they reuse its space: less LDS per
-    // env, more waves per CU.  Up to 4 players they fit (P*S <= 4S); the
-    // 16-byte read slack past the last plane then falls on the owner row,
-    // whose bytes the funnel shifts discard.
-    if (g.P <= 4) {
-        L.code = smem;
-    } else {
-        L.code = smem + o; o += g.P * g.S + 16;
-    }
     L.obm = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.vis = reinterpret_cast<uint64_t *>(smem + o); o += 8 * 16 * g.P;
     L.gbm = reinterpret_cast<uint64_t *>(smem + o);
@@ -510,11 +496,32 @@ __device__ __forceinline__ uint32_t code_quad(const Lds &L, const Geom &g, int p
            ((gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
 }
 
-// One obs byte (slow path for dwords that straddle two planes).
+// Code byte of one cell for player p (same bits as code_quad), for the few
+// output dwords that hold bytes of two planes.
+__device__ __forceinline__ uint32_t code_cell(const Lds &L, int p, uint32_t ally, int c)
+{
+    const int o = L.owner[c];
+    const uint32_t t = L.type[c];
+    const bool vis = (L.vis[p * 16 + (c >> 6)] >> (c & 63)) & 1ull;
+    const bool neutral = o < 0;
+    const bool enemy = !neutral && o != p && (uint32_t)o != ally;
+    uint32_t code = (o == p) ? 1u : 0u;
+    if (vis) {
+        code |= (enemy ? 2u : 0u) | ((neutral && t != (uint32_t)MOUNTAIN) ? 4u : 0u) |
+                (t == (uint32_t)MOUNTAIN ? 8u : 0u) | (t == (uint32_t)CASTLE ? 16u : 0u) |
+                (t == (uint32_t)GENERAL ? 32u : 0u);
+    } else {
+        code |= 64u;
+    }
+    return code;
+}
+
+// Observation byte b of the env block (plane b / HW, cell b % HW).
 __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32_t b)
 {
     const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-    const uint32_t cd = L.code[p * g.S + c];
+    const uint32_t ally = g.mode == MODE_2V2 ? (p ^ 2u) : p;
+    const uint32_t cd = code_cell(L, (int)p, ally, (int)c);
     return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
 }
 
@@ -709,45 +716,60 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
                 }
             }
         }
-    } else {
-        // ---- per-(player, cell) code bytes staged in LDS
-        const int nq = (g.HW + 3) >> 2;
+    } else if (io.obs != nullptr) {
+        // ---- other plane sizes: plane (p, ch) starts m = (8p + ch) * HW mod 4
+        // bytes into a dword.  Lane j computes quad j's code bytes as above;
+        // output dword j of the plane takes the last m bytes of quad j-1 (from
+        // lane j-1 by a shuffle, or carried over from the previous round) and
+        // the first 4-m of quad j.  Dwords that hold bytes of two planes are
+        // left to a byte-wise pass after the loop.
+        const int nq = g.HW >> 2;                                   // whole quads
+        const int rounds = (nq + 1 + kWave - 1) / kWave;            // quads 0 .. nq
+        uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
         for (int p = 0; p < g.P; ++p) {
             const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
-            uint32_t *cw = reinterpret_cast<uint32_t *>(L.code + p * g.S);
-            for (int q = lane; q < nq; q += kWave) cw[q] = code_quad(L, g, p, ally, q);
+            uint32_t carry[8];
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) carry[ch] = 0u;
+            for (int r = 0; r < rounds; ++r) {
+                const int j = r * kWave + lane;
+                const int qj = j < (g.S >> 2) ? j : 0;              // stays inside the padded row
+                const uint32_t code = code_quad(L, g, p, ally, qj);
+                const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[qj];
+#pragma unroll
+                for (int ch = 0; ch < 8; ++ch) {
+                    const uint32_t cur = ch < 7 ? (code >> ch) & 0x01010101u : ac & vismask(code);
+                    uint32_t prev = shfl32(cur, lane - 1);
+                    if (lane == 0) prev = carry[ch];
+                    carry[ch] = (uint32_t)readlane((int)cur, kWave - 1);
+                    const uint32_t B0 = (uint32_t)((p * 8 + ch) * g.HW);
+                    const uint32_t m = B0 & 3u, d0 = B0 >> 2;
+                    // interior: bytes 4j - m .. 4j - m + 3 all inside the plane
+                    const bool interior = (4 * j >= (int)m) && (4 * j + 4 - (int)m <= g.HW);
+                    if (interior) {
+                        // plain (cached) store: the 32-byte sectors at plane
+                        // boundaries are shared by two stores, and the cache
+                        // merges them; nontemporal partial-sector writes
+                        // measured 1.5x slower on these shapes
+                        const uint32_t v = m == 0 ? cur : __builtin_amdgcn_alignbyte(cur, prev, 4u - m);
+                        ob[d0 + j] = v;
+                    }
+                }
+            }
+        }
+        // the dwords across plane boundaries: at most one per plane start
+        const int n_planes = g.P * 8;
+        for (int i = 1 + lane; i < n_planes; i += kWave) {
+            const uint32_t B0 = (uint32_t)(i * g.HW);
+            if ((B0 & 3u) == 0) continue;
+            const uint32_t b = B0 & ~3u;
+            uint32_t v = 0;
+#pragma nounroll
+            for (int k = 0; k < 4; ++k) v |= obs_byte(L, g, b + k) << (8 * k);
+            ob[b >> 2] = v;
         }
     }
     wave_sync();
-
-    // ---- observation stream for the other plane sizes: one output dword per
-    // lane and round (consecutive lanes read consecutive LDS dwords: no bank
-    // conflicts), its 4 code bytes funnel-shifted out of two aligned dwords
-    if (io.obs != nullptr && !quad_obs) {
-        const uint32_t B = (uint32_t)(g.P * 8 * g.HW);
-        uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
-        for (uint32_t k = lane; k < (B >> 2); k += kWave) {
-            const uint32_t b = k << 2;
-            const uint32_t q = div_hw(b, g), c = b - q * g.HW, p = q >> 3, ch = q & 7;
-            uint32_t v;
-            if (c + 4 <= (uint32_t)g.HW) {
-                const uint32_t *cw = reinterpret_cast<const uint32_t *>(L.code + p * g.S) + (c >> 2);
-                const uint32_t cd = __builtin_amdgcn_alignbyte(cw[1], cw[0], c & 3);
-                if (ch < 7) {
-                    v = (cd >> ch) & 0x01010101u;
-                } else {
-                    const uint32_t *aw = reinterpret_cast<const uint32_t *>(L.armyc) + (c >> 2);
-                    v = __builtin_amdgcn_alignbyte(aw[1], aw[0], c & 3) & vismask(cd);
-                }
-            } else {
-                // a dword across a plane boundary (one per plane at most)
-                v = 0;
-#pragma nounroll
-                for (int j = 0; j < 4; ++j) v |= obs_byte(L, g, b + j) << (8 * j);
-            }
-            st_nt(ob + k, v);
-        }
-    }
 
     // ---- fused random actor for the next step, on the final state
     if (ACT && io.next_actions != nullptr)

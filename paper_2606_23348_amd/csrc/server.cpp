@@ -125,7 +125,9 @@ struct gen_server {
     std::vector<Slot> slots;
     uint64_t next_group = 1, next_ticket = 1;
     std::thread sched;
-    bool stop = false;
+    std::atomic<bool> stop{false};
+    std::atomic<int64_t> n_queued{0};                  // requests in `queue` (lock-free hint)
+    std::atomic<uint64_t> n_submitted{0};              // submits so far (lock-free hint)
     std::string error;                                 // sticky scheduler error
     // stats
     uint64_t st_requests = 0, st_frames = 0, st_launches = 0, st_refused = 0, st_launch_envs = 0;
@@ -188,29 +190,62 @@ void scheduler(gen_server *sp)
 {
     gen_server &s = *sp;
     (void)hipSetDevice(s.device);
-    std::unique_lock<std::mutex> lk(s.mu);
+    const size_t ns = s.slots.size();
+    uint64_t last_submits = UINT64_MAX;   // submits seen by the last attempt that launched nothing
+    int64_t retry_at = INT64_MAX;         // when that attempt's batching window closes
     while (true) {
-        bool progressed = false;
-        // completions
-        for (auto &sl : s.slots) {
+        // Completions are polled without the lock (only this thread touches
+        // the slots), and the lock is taken only when there is something to
+        // do, so client threads are not starved while launches run.
+        int n_busy = 0;
+        bool done[4] = {false, false, false, false};
+        hipError_t qs[4] = {hipSuccess, hipSuccess, hipSuccess, hipSuccess};
+        bool any_done = false;
+        for (size_t i = 0; i < ns; ++i) {
+            Slot &sl = s.slots[i];
             if (!sl.busy) continue;
             const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipSuccess) {
-                complete_slot(s, sl, 0);
-                progressed = true;
-            } else if (q != hipErrorNotReady) {
-                s.error = std::string("launch failed: ") + hipGetErrorString(q);
-                complete_slot(s, sl, GEN_EHIP);
-                progressed = true;
+            if (q == hipErrorNotReady) { ++n_busy; continue; }
+            done[i] = true;
+            qs[i] = q;
+            any_done = true;
+        }
+        const bool queued = s.n_queued.load(std::memory_order_acquire) > 0;
+        const uint64_t submits = s.n_submitted.load(std::memory_order_acquire);
+        const bool try_launch = n_busy < (int)ns && queued && (submits != last_submits || now_ns() >= retry_at);
+        if (!any_done && !try_launch) {
+            if (s.stop.load() && n_busy == 0) {
+                // shutting down: leave once nothing more can be launched
+                std::lock_guard<std::mutex> g(s.mu);
+                if (s.queue.empty() || !s.error.empty()) break;
+            }
+            if (n_busy > 0 || queued) {
+                // work pending: keep polling (a timed sleep overshoots by tens
+                // of microseconds, which every request's latency would pay)
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> lk(s.mu);
+                s.cv_sched.wait_for(lk, std::chrono::milliseconds(5),
+                                    [&] { return s.n_queued.load() > 0 || s.stop.load(); });
+            }
+            continue;
+        }
+        std::unique_lock<std::mutex> lk(s.mu);
+        for (size_t i = 0; i < ns; ++i) {
+            if (!done[i]) continue;
+            if (qs[i] == hipSuccess) {
+                complete_slot(s, s.slots[i], 0);
+            } else {
+                s.error = std::string("launch failed: ") + hipGetErrorString(qs[i]);
+                complete_slot(s, s.slots[i], GEN_EHIP);
             }
         }
-        if (s.stop && s.queue.empty() && std::none_of(s.slots.begin(), s.slots.end(), [](const Slot &x) { return x.busy; }))
-            break;
         // form a launch from the queue: every request whose group is free
         Slot *free_slot = nullptr;
         for (auto &sl : s.slots)
             if (!sl.busy) { free_slot = &sl; break; }
         bool launch_now = free_slot && !s.queue.empty() && s.error.empty();
+        retry_at = INT64_MAX;
         if (launch_now) {
             // Launch when no other open group can still join (every group is
             // either on the GPU or has a request waiting), when the ready
@@ -230,18 +265,26 @@ void scheduler(gen_server *sp)
                 if (x.busy) inflight += (int64_t)x.envs;
             const int64_t idle = s.open_envs - inflight - ready;
             const int64_t want = s.min_batch_envs > 0 ? s.min_batch_envs : std::max<int64_t>(1, s.open_envs / 4);
-            launch_now = ready > 0 && (idle <= 0 || ready >= want || now_ns() - oldest >= s.max_wait_us * 1000);
+            const int64_t deadline = oldest == INT64_MAX ? INT64_MAX : oldest + s.max_wait_us * 1000;
+            launch_now = ready > 0 && (idle <= 0 || ready >= want || now_ns() >= deadline);
+            if (!launch_now && ready > 0) retry_at = deadline;
         }
+        uint32_t n_req = 0;
         if (launch_now) {
             Slot &sl = *free_slot;
-            uint32_t n_req = 0, wg = 0, lds = 0;
+            uint32_t wg = 0, lds = 0;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
                 auto tk = s.tickets.find(*it);
-                if (tk == s.tickets.end() || tk->second.status != 1) { it = s.queue.erase(it); continue; }
+                if (tk == s.tickets.end() || tk->second.status != 1) {
+                    it = s.queue.erase(it);
+                    s.n_queued.fetch_sub(1, std::memory_order_release);
+                    continue;
+                }
                 auto gi = s.groups.find(tk->second.group);
                 if (gi == s.groups.end() || gi->second->closing) {
                     tk->second.status = GEN_ENOTFOUND;
                     it = s.queue.erase(it);
+                    s.n_queued.fetch_sub(1, std::memory_order_release);
                     continue;
                 }
                 Group &g = *gi->second;
@@ -253,6 +296,7 @@ void scheduler(gen_server *sp)
                 lds = std::max(lds, g.pool->lds_per_wave);
                 ++n_req;
                 it = s.queue.erase(it);
+                s.n_queued.fetch_sub(1, std::memory_order_release);
             }
             if (n_req > 0) {
                 sl.busy = true;
@@ -265,28 +309,14 @@ void scheduler(gen_server *sp)
                                               hipMemcpyHostToDevice, sl.stream);
                 if (e == hipSuccess) e = gen::launch_serve(s.arena, d_table, n_req, wg, lds, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
-                lk.lock();
                 if (e != hipSuccess) {
+                    lk.lock();
                     s.error = std::string("launch failed: ") + hipGetErrorString(e);
                     complete_slot(s, sl, GEN_EHIP);
                 }
-                progressed = true;
             }
         }
-        if (!progressed) {
-            // With work pending (a launch on the GPU or requests in the queue)
-            // keep polling: a timed sleep overshoots by tens of microseconds,
-            // which would add to every request's latency.  Fully idle: block
-            // until a client submits.
-            const bool inflight = std::any_of(s.slots.begin(), s.slots.end(), [](const Slot &x) { return x.busy; });
-            if (inflight || !s.queue.empty()) {
-                lk.unlock();
-                std::this_thread::yield();
-                lk.lock();
-            } else {
-                s.cv_sched.wait_for(lk, std::chrono::milliseconds(5));
-            }
-        }
+        last_submits = n_req > 0 ? UINT64_MAX : submits;
     }
 }
 
@@ -438,6 +468,8 @@ int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
         const uint64_t tk = s->next_ticket++;
         s->tickets[tk] = Ticket{group, now_ns(), 1};
         s->queue.push_back(tk);
+        s->n_queued.fetch_add(1, std::memory_order_release);
+        s->n_submitted.fetch_add(1, std::memory_order_release);
         *ticket = tk;
     }
     s->cv_sched.notify_one();
@@ -619,38 +651,71 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
         struct Cl { int32_t c, gi, k; Clock::time_point next; };
         std::vector<Cl> cl;
         for (int32_t c = t; c < n_clients; c += n_threads) cl.push_back({c, 0, 1, t0 + gap(c, 0)});
+        std::vector<Cl *> ready;
+        ready.reserve(cl.size());
         while (!failure) {
             const auto now = Clock::now();
             if (now >= t_end) break;
-            bool progressed = false;
+            // 1. clients whose timer fired and whose group has no request on the GPU
+            ready.clear();
             for (auto &x : cl) {
-                if (failure) break;
                 if (x.next >= t_end || now < x.next) continue;
                 ClientGroup &grp = cg[(size_t)x.c][(size_t)x.gi];
+                if (grp.outstanding && grp.g->completed.load(std::memory_order_acquire) <= grp.mark) continue;
+                ready.push_back(&x);
+            }
+            if (ready.empty()) {
+                std::this_thread::yield();
+                continue;
+            }
+            // 2. groups due for replacement are closed and reopened one by one
+            for (Cl *x : ready) {
+                ClientGroup &grp = cg[(size_t)x->c][(size_t)x->gi];
+                if (steps_per_group <= 0 || grp.steps + (grp.outstanding ? 1 : 0) < steps_per_group) continue;
                 if (grp.outstanding) {
-                    if (grp.g->completed.load(std::memory_order_acquire) <= grp.mark) continue;
                     const int rc = gen_server_wait(s, grp.ticket, kDriveWaitUs);
                     if (rc != GEN_OK) { failure = rc; break; }
                     grp.outstanding = false;
                     grp.steps += 1;
                 }
-                if (steps_per_group > 0 && grp.steps >= steps_per_group) {
-                    if (gen_server_close(s, grp.id) != GEN_OK) { failure = GEN_EHIP; break; }
-                    grp.env_base = reopen_base.fetch_add((uint64_t)grp.n_envs);
-                    const int rc = gen_server_open(s, seed, grp.env_base, grp.n_envs, h_specs + grp.spec_begin, common,
-                                                   1, actor_seed, &grp.id);
-                    if (rc != GEN_OK) { failure = rc; break; }
-                    grp.g = group_of(s, grp.id);
-                    grp.steps = 0;
-                }
-                grp.mark = grp.g->completed.load(std::memory_order_acquire);
-                if (gen_server_submit(s, grp.id, &grp.ticket) != GEN_OK) { failure = GEN_EHIP; break; }
-                grp.outstanding = true;
-                x.gi = (x.gi + 1) % (int32_t)cg[(size_t)x.c].size();
-                x.next += gap(x.c, x.k++);
-                progressed = true;
+                if (gen_server_close(s, grp.id) != GEN_OK) { failure = GEN_EHIP; break; }
+                grp.env_base = reopen_base.fetch_add((uint64_t)grp.n_envs);
+                const int rc = gen_server_open(s, seed, grp.env_base, grp.n_envs, h_specs + grp.spec_begin, common,
+                                               1, actor_seed, &grp.id);
+                if (rc != GEN_OK) { failure = rc; break; }
+                grp.g = group_of(s, grp.id);
+                grp.steps = 0;
             }
-            if (!progressed) std::this_thread::yield();
+            if (failure) break;
+            // 3. collect the finished tickets and submit the next requests
+            // under one lock acquisition for the whole batch
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (!s->error.empty()) { failure = GEN_EHIP; break; }
+                for (Cl *x : ready) {
+                    ClientGroup &grp = cg[(size_t)x->c][(size_t)x->gi];
+                    if (grp.outstanding) {
+                        auto it = s->tickets.find(grp.ticket);
+                        if (it == s->tickets.end() || it->second.status != 0) { failure = GEN_EHIP; break; }
+                        s->tickets.erase(it);
+                        grp.outstanding = false;
+                        grp.steps += 1;
+                    }
+                    auto gi = s->groups.find(grp.id);
+                    if (gi == s->groups.end() || gi->second->closing) { failure = GEN_ENOTFOUND; break; }
+                    grp.mark = grp.g->completed.load(std::memory_order_acquire);
+                    const uint64_t tk = s->next_ticket++;
+                    s->tickets[tk] = Ticket{grp.id, now_ns(), 1};
+                    s->queue.push_back(tk);
+                    s->n_queued.fetch_add(1, std::memory_order_release);
+                    s->n_submitted.fetch_add(1, std::memory_order_release);
+                    grp.ticket = tk;
+                    grp.outstanding = true;
+                    x->gi = (x->gi + 1) % (int32_t)cg[(size_t)x->c].size();
+                    x->next += gap(x->c, x->k++);
+                }
+            }
+            s->cv_sched.notify_one();
         }
         for (auto &x : cl)
             for (auto &grp : cg[(size_t)x.c])
