@@ -174,13 +174,24 @@ __device__ __forceinline__ uint32_t div_hw(uint32_t b, const Geom &g)
 // and the positions that are real cells (< HW).
 struct ColMasks { uint64_t col0, colL, valid; };
 
+// Bits 0, W, 2W, ... of a word (wave-uniform W: a short scalar loop).
+__device__ __forceinline__ uint64_t col_pattern(int W)
+{
+    uint64_t m = 0;
+    for (int b = 0; b < 64; b += W) m |= 1ull << b;
+    return m;
+}
+
 __device__ __forceinline__ ColMasks col_masks(int w, const Geom &g)
 {
-    ColMasks m{0, 0, 0};
-    const int r0 = (64 * w) % g.W;
-    for (int b = (g.W - r0) % g.W; b < 64; b += g.W) m.col0 |= 1ull << b;
-    for (int b = (2 * g.W - 1 - r0) % g.W; b < 64; b += g.W) m.colL |= 1ull << b;
-    const int left = g.HW - 64 * w;
+    ColMasks m;
+    const uint64_t pat = col_pattern(g.W);
+    const int c0 = 64 * w;                             // first cell of the word (< 1024)
+    const int r0 = c0 - g.W * div_w(c0, g);           // its column
+    // cells of column 0 sit at positions == -r0 (mod W), of column W-1 at W-1-r0
+    m.col0 = pat << (r0 == 0 ? 0 : g.W - r0);
+    m.colL = pat << (g.W - 1 - r0);
+    const int left = g.HW - c0;
     m.valid = left >= 64 ? ~0ull : left <= 0 ? 0ull : ((1ull << left) - 1);
     return m;
 }

@@ -14,6 +14,7 @@ namespace gen {
 //   obm   u64 [P][16]                 (cells owned by each player)
 //   vis   u64 [P][16]                 (visible cell bitmaps)
 //   gbm   u64 [3][16] + int32 [8]      (map generator scratch bitmaps, general cells)
+//         + u64 [4]                    (the actor's Philox block, computed early)
 struct Lds {
     int32_t *army;
     int8_t *owner;
@@ -24,7 +25,7 @@ struct Lds {
 
 uint32_t lds_bytes_for(int S, int P)
 {
-    return (uint32_t)(4 * S + S + S + (S + 16) + 8 * 16 * (2 * P + 3) + 32);
+    return (uint32_t)(4 * S + S + S + (S + 16) + 8 * 16 * (2 * P + 3) + 32 + 32);
 }
 
 __device__ __forceinline__ Lds carve(uint8_t *smem, const Geom &g)
@@ -399,7 +400,8 @@ __device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_
 // uniform pick is located by a prefix over words and a binary search over
 // the bits of one word.  own: [P][16] words, pass/big: [16] words in LDS.
 __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *pass, const uint64_t *big,
-                           uint32_t alive, uint64_t actor_seed, uint64_t step_idx, uint64_t env_id, int32_t *act_out)
+                           uint32_t alive, uint64_t actor_seed, uint64_t step_idx, uint64_t env_id, int32_t *act_out,
+                           const uint64_t *blk = nullptr)
 {
     const int lane = lane_id();
     const int NW = g.NW, W = g.W;
@@ -417,8 +419,13 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
     // shuffle keeps the block on the vector unit: as a wave-uniform value the
     // compiler would run it on the scalar unit, whose long 64-bit multiply
     // chains cost more wave time than the vector version.
-    uint64_t r0 = shfl64(env_id, lane), r1 = step_idx, r2 = 0, r3 = 0;
-    philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
+    uint64_t r0, r1, r2, r3;
+    if (blk != nullptr) {                        // computed earlier by the caller (in LDS)
+        r0 = blk[0]; r1 = blk[1]; r2 = blk[2]; r3 = blk[3];
+    } else {
+        r0 = shfl64(env_id, lane); r1 = step_idx; r2 = 0; r3 = 0;
+        philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
+    }
     for (int p0 = 0; p0 < g.P; p0 += ppr) {
         const int p = p0 + lp;
         const bool valid = lp < ppr && p < g.P;
@@ -564,18 +571,54 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
         write_type = true;
     } else {
         s = *io.sc;
-        // state HBM -> LDS, 16-byte loads
         const int n16 = g.S >> 4;
         const uint4 *go = reinterpret_cast<const uint4 *>(io.owner);
         const uint4 *gt = reinterpret_cast<const uint4 *>(io.type);
         const uint4 *ga = reinterpret_cast<const uint4 *>(io.army);
-        for (int i = lane; i < n16; i += kWave) {
-            reinterpret_cast<uint4 *>(L.owner)[i] = go[i];
-            reinterpret_cast<uint4 *>(L.type)[i] = gt[i];
-        }
-        for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(L.army)[i] = ga[i];
         int32_t act = 0;
-        if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
+        if constexpr (ACT) {
+            // state HBM -> registers (16-byte loads; S <= 1024 cells, so one
+            // owner and one type chunk and at most four army chunks per
+            // lane; indexes are clamped rather than the loads predicated:
+            // lanes past the end re-read the last chunk and skip the store)
+            const int na = 4 * n16;
+            const uint4 vo = go[min(lane, n16 - 1)];
+            const uint4 vt = gt[min(lane, n16 - 1)];
+            const uint4 va0 = ga[min(lane, na - 1)];
+            const uint4 va1 = ga[min(lane + 64, na - 1)];
+            const uint4 va2 = ga[min(lane + 128, na - 1)];
+            const uint4 va3 = ga[min(lane + 192, na - 1)];
+            if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
+            // the actor's Philox block does not depend on the state:
+            // computing it while the loads are in flight hides their
+            // latency; it waits in LDS until the actor runs
+            if (io.next_actions != nullptr) {
+                const uint64_t tick = (uint64_t)s.tick + ((KIND == K_STEP && io.use_tick) ? 1u : 0u);
+                uint64_t r0 = shfl64(env_id, lane), r1 = io.use_tick ? tick : io.actor_step, r2 = 0, r3 = 0;
+                philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
+                if (lane == 0) {
+                    uint64_t *pb = L.gbm + 52;
+                    pb[0] = r0; pb[1] = r1; pb[2] = r2; pb[3] = r3;
+                }
+            }
+            if (lane < n16) {
+                reinterpret_cast<uint4 *>(L.owner)[lane] = vo;
+                reinterpret_cast<uint4 *>(L.type)[lane] = vt;
+            }
+            uint4 *la = reinterpret_cast<uint4 *>(L.army);
+            if (lane < na) la[lane] = va0;
+            if (lane + 64 < na) la[lane + 64] = va1;
+            if (lane + 128 < na) la[lane + 128] = va2;
+            if (lane + 192 < na) la[lane + 192] = va3;
+        } else {
+            // state HBM -> LDS, 16-byte loads
+            for (int i = lane; i < n16; i += kWave) {
+                reinterpret_cast<uint4 *>(L.owner)[i] = go[i];
+                reinterpret_cast<uint4 *>(L.type)[i] = gt[i];
+            }
+            for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(L.army)[i] = ga[i];
+            if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
+        }
         wave_sync();
         if (KIND == K_STEP) {
             if (io.use_tick) s.tick += 1;
@@ -774,7 +817,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     // ---- fused random actor for the next step, on the final state
     if (ACT && io.next_actions != nullptr)
         actor_wave(g, L.obm, L.gbm, L.gbm + 16, s.alive, actor_seed, io.use_tick ? s.tick : io.actor_step, env_id,
-                   io.next_actions);
+                   io.next_actions, KIND != K_RESET ? L.gbm + 52 : nullptr);
 
     // ---- rewards, done, scalars
     if (KIND == K_STEP) {
