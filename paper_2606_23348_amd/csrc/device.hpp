@@ -110,6 +110,19 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 }
 
 // ---------------------------------------------------------------- Philox4x64-10
+// 64x64 -> 128-bit product as four 32x32+64 multiply-adds (v_mad_u64_u32 on
+// the vector unit): t = a0 m0, u = a1 m0 + hi(t), v = a0 m1 + lo(u); then
+// a m = lo(t) + 2^32 lo(v) + 2^64 (a1 m1 + hi(u) + hi(v)), no sum overflowing.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t m, uint64_t &lo, uint64_t &hi)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+    const uint64_t t = (uint64_t)a0 * m0;
+    const uint64_t u = (uint64_t)a1 * m0 + (t >> 32);
+    const uint64_t v = (uint64_t)a0 * m1 + (uint32_t)u;
+    hi = (uint64_t)a1 * m1 + (u >> 32) + (v >> 32);
+    lo = (v << 32) | (uint32_t)t;
+}
+
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
 // (SC'11): ten rounds of two 64x64->128 multiplies; the key advances by the
 // two Weyl constants between rounds.
@@ -120,8 +133,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64
     const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
-        const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
+        uint64_t lo0, hi0, lo1, hi1;
+        mulhilo64(x0, M0, lo0, hi0);
+        mulhilo64(x2, M1, lo1, hi1);
         const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
         x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
         k0 += W0; k1 += W1;

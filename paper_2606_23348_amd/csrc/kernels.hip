@@ -480,30 +480,83 @@ enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
 // other size; OBS_RUNTIME decides per env from the geometry (mixed shapes).
 enum { OBS_QUAD = 0, OBS_STREAM = 1, OBS_RUNTIME = -1 };
 
-__device__ __forceinline__ uint32_t vismask(uint32_t code4)
+// Player-independent bits of the four cells of quad q, one 0x01 per cell
+// byte (SWAR over the owner and type bytes).
+struct QuadCells {
+    uint32_t o4;        // owner bytes
+    uint32_t neutral;   // no owner
+    uint32_t plain_n;   // no owner and not a mountain
+    uint32_t mtn, cas, gen;
+};
+
+__device__ __forceinline__ QuadCells quad_cells(const Lds &L, int q)
 {
-    return (((code4 >> 6) & 0x01010101u) ^ 0x01010101u) * 0xFFu;
+    QuadCells c;
+    c.o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
+    const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
+    c.neutral = (c.o4 >> 7) & 0x01010101u;
+    c.mtn = t4 & ~(t4 >> 1) & 0x01010101u;
+    c.cas = (t4 >> 1) & ~t4 & 0x01010101u;
+    c.gen = t4 & (t4 >> 1) & 0x01010101u;
+    c.plain_n = c.neutral & ~c.mtn;
+    return c;
 }
 
-// Code bytes of the four cells of quad q for player p (bit k = obs channel k,
-// k < 7; reading R16): SWAR over the owner and type bytes and 4 vision bits.
-__device__ __forceinline__ uint32_t code_quad(const Lds &L, const Geom &g, int p, uint32_t ally, int q)
+// The eight observation dwords of quad q for player p (reading R16): one
+// byte per cell, channel k in v[k].  ac: the quad's army bytes clamped to
+// 255.  In 2v2 `ally` is p's teammate, otherwise p itself.
+__device__ __forceinline__ void quad_planes(const Lds &L, const QuadCells &c, uint32_t ac, int p, uint32_t ally,
+                                            int q, uint32_t v[8])
 {
-    const uint32_t o4 = reinterpret_cast<const uint32_t *>(L.owner)[q];
-    const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
     const uint32_t vb = (uint32_t)(L.vis[p * 16 + (q >> 4)] >> ((q & 15) * 4)) & 0xFu;
     const uint32_t visb = spread4(vb);
-    const uint32_t eqp = bytes_eq(o4, (uint32_t)p), eqa = bytes_eq(o4, ally);
-    const uint32_t neutral = (o4 >> 7) & 0x01010101u;
-    const uint32_t enemy = (neutral ^ 0x01010101u) & ~eqp & ~eqa;
-    const uint32_t mtn = t4 & ~(t4 >> 1) & 0x01010101u;
-    const uint32_t cas = (t4 >> 1) & ~t4 & 0x01010101u;
-    const uint32_t gen = t4 & (t4 >> 1) & 0x01010101u;
-    return eqp | ((enemy & visb) << 1) | ((neutral & ~mtn & visb) << 2) | ((mtn & visb) << 3) | ((cas & visb) << 4) |
-           ((gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
+    const uint32_t eqp = bytes_eq(c.o4, (uint32_t)p);
+    const uint32_t eqa = ally == (uint32_t)p ? eqp : bytes_eq(c.o4, ally);
+    v[0] = eqp;
+    v[1] = (c.neutral ^ 0x01010101u) & ~eqp & ~eqa & visb;
+    v[2] = c.plain_n & visb;
+    v[3] = c.mtn & visb;
+    v[4] = c.cas & visb;
+    v[5] = c.gen & visb;
+    v[6] = visb ^ 0x01010101u;
+    v[7] = ac & (visb * 0xFFu);
 }
 
-// Code byte of one cell for player p (same bits as code_quad), for the few
+// Quad q's dwords of player p's eight planes into the env's observation
+// block ([P][8][HW] bytes), nontemporal.
+__device__ __forceinline__ void quad_store(const Lds &L, const Geom &g, uint8_t *obs, const QuadCells &qc, uint32_t ac,
+                                           int p, int q)
+{
+    const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
+    uint32_t v[8];
+    quad_planes(L, qc, ac, p, ally, q, v);
+    uint8_t *pb = obs + (size_t)p * 8 * g.HW;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) st_nt(reinterpret_cast<uint32_t *>(pb + ch * g.HW) + q, v[ch]);
+}
+
+// Code bytes of the four cells of quad q for player p (bit k = channel k,
+// k < 7; bit 6 set = fog): one register per quad for the stream writer,
+// which extracts the channels one at a time.
+__device__ __forceinline__ uint32_t code_quad(const Lds &L, int p, uint32_t ally, int q)
+{
+    const QuadCells c = quad_cells(L, q);
+    const uint32_t vb = (uint32_t)(L.vis[p * 16 + (q >> 4)] >> ((q & 15) * 4)) & 0xFu;
+    const uint32_t visb = spread4(vb);
+    const uint32_t eqp = bytes_eq(c.o4, (uint32_t)p);
+    const uint32_t eqa = ally == (uint32_t)p ? eqp : bytes_eq(c.o4, ally);
+    const uint32_t enemy = (c.neutral ^ 0x01010101u) & ~eqp & ~eqa;
+    return eqp | ((enemy & visb) << 1) | ((c.plain_n & visb) << 2) | ((c.mtn & visb) << 3) | ((c.cas & visb) << 4) |
+           ((c.gen & visb) << 5) | ((visb ^ 0x01010101u) << 6);
+}
+
+// Army bytes of a quad on the cells its code bytes mark visible.
+__device__ __forceinline__ uint32_t army_visible(uint32_t ac, uint32_t code4)
+{
+    return ac & ((((code4 >> 6) & 0x01010101u) ^ 0x01010101u) * 0xFFu);
+}
+
+// Code byte of one cell for player p (bit k = channel k < 7, as quad_planes), for the few
 // output dwords that hold bytes of two planes.
 __device__ __forceinline__ uint32_t code_cell(const Lds &L, int p, uint32_t ally, int c)
 {
@@ -738,30 +791,32 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     wave_sync();
 
     // Planes of a multiple of 4 cells: each lane takes 4 cells, computes their
-    // code bytes in registers and writes them straight into all 8 channel
-    // planes (4-byte stores, 256 contiguous bytes per wave store).  Other
-    // shapes stage the code bytes in LDS for the chunk writers below.
+    // bytes of all 8 channel planes in registers and stores them directly
+    // (4-byte stores, 256 contiguous bytes per wave store).  Other shapes
+    // realign the same dwords with lane shuffles below.
     const bool quad_obs =
         OBSV == OBS_QUAD || (OBSV == OBS_RUNTIME && (g.HW & 3) == 0);
     if (quad_obs) {
         if (io.obs != nullptr) {
+            // Loop order, as measured: quads outer (a quad's owner and type
+            // bits decoded once for all players) in the plain batch kernels,
+            // players outer in the mixed-shape pool, where it was faster.
             const int nq = g.HW >> 2;
-            for (int p = 0; p < g.P; ++p) {
-                const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
-                uint8_t *pb = io.obs + (size_t)p * 8 * g.HW;
+            if (OBSV == OBS_QUAD) {
                 for (int q = lane; q < nq; q += kWave) {
-                    const uint32_t code = code_quad(L, g, p, ally, q);
+                    const QuadCells qc = quad_cells(L, q);
                     const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[q];
-#pragma unroll
-                    for (int ch = 0; ch < 7; ++ch)
-                        st_nt(reinterpret_cast<uint32_t *>(pb + ch * g.HW) + q, (code >> ch) & 0x01010101u);
-                    st_nt(reinterpret_cast<uint32_t *>(pb + 7 * g.HW) + q, ac & vismask(code));
+                    for (int p = 0; p < g.P; ++p) quad_store(L, g, io.obs, qc, ac, p, q);
                 }
+            } else {
+                for (int p = 0; p < g.P; ++p)
+                    for (int q = lane; q < nq; q += kWave)
+                        quad_store(L, g, io.obs, quad_cells(L, q), reinterpret_cast<const uint32_t *>(L.armyc)[q], p, q);
             }
         }
     } else if (io.obs != nullptr) {
         // ---- other plane sizes: plane (p, ch) starts m = (8p + ch) * HW mod 4
-        // bytes into a dword.  Lane j computes quad j's code bytes as above;
+        // bytes into a dword.  Lane j computes quad j's code bytes (code_quad);
         // output dword j of the plane takes the last m bytes of quad j-1 (from
         // lane j-1 by a shuffle, or carried over from the previous round) and
         // the first 4-m of quad j.  Dwords that hold bytes of two planes are
@@ -777,11 +832,11 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             for (int r = 0; r < rounds; ++r) {
                 const int j = r * kWave + lane;
                 const int qj = j < (g.S >> 2) ? j : 0;              // stays inside the padded row
-                const uint32_t code = code_quad(L, g, p, ally, qj);
+                const uint32_t code = code_quad(L, p, ally, qj);
                 const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[qj];
 #pragma unroll
                 for (int ch = 0; ch < 8; ++ch) {
-                    const uint32_t cur = ch < 7 ? (code >> ch) & 0x01010101u : ac & vismask(code);
+                    const uint32_t cur = ch < 7 ? (code >> ch) & 0x01010101u : army_visible(ac, code);
                     uint32_t prev = shfl32(cur, lane - 1);
                     if (lane == 0) prev = carry[ch];
                     carry[ch] = (uint32_t)readlane((int)cur, kWave - 1);
@@ -838,8 +893,15 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     }
 }
 
+// The step kernels for planes of a multiple of 4 cells without the
+// scoreboard are limited to the registers of 8 waves per SIMD (the default
+// budget of 106 scalar registers allows 7); the extra scalar spills go to
+// vector-register lanes and cost less than the lost occupancy (measured).
+// The scoreboard kernels would spill vector registers to scratch under that
+// limit, and the other plane sizes measured slower at 25x25; they keep the
+// default.
 template <int KIND, int OBSV, bool SB, bool ACT>
-__global__ __launch_bounds__(64) void k_env(EnvArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((SB || OBSV != OBS_QUAD) ? 1 : 8, 8))) void k_env(EnvArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const int e = blockIdx.x;
