@@ -72,6 +72,10 @@ def lib():
         _lib.orc_philox4x64_10.restype = None
         _lib.orc_draw.argtypes = [u64] * 6
         _lib.orc_draw.restype = ctypes.c_uint32
+        _lib.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        _lib.orc_philox4x32_10.restype = None
+        _lib.orc_actor_draw.argtypes = [u64, u64, u64, ctypes.c_int]
+        _lib.orc_actor_draw.restype = ctypes.c_uint32
         _lib.orc_reset_batch.argtypes = [vp, i32, vp, vp]
         _lib.orc_step_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         _lib.orc_observe_batch.argtypes = [vp, i32, vp, vp]
@@ -243,3 +247,17 @@ def philox(ctr, key) -> np.ndarray:
 
 def draw(seed: int, domain: int, c0: int, c1: int, c2: int, j: int) -> int:
     return int(lib().orc_draw(seed, domain, c0, c1, c2, j))
+
+
+def philox32(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of a 4-word counter and a 2-word key (uint32)."""
+    c = np.ascontiguousarray(np.asarray(ctr, np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, np.uint32))
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def actor_draw(seed_act: int, env_id: int, step: int, p: int) -> int:
+    """The random actor's 32-bit draw for player p (reading R15)."""
+    return int(lib().orc_actor_draw(seed_act, env_id, step, p))

@@ -121,6 +121,49 @@ uint32_t orc_draw(uint64_t seed, uint64_t domain, uint64_t c0, uint64_t c1, uint
     return (j % 2 == 0) ? (uint32_t)(w & 0xFFFFFFFFu) : (uint32_t)(w >> 32);
 }
 
+/* ======================================================================
+ * Philox4x32-10 (same paper as above): the 32-bit member of the family.
+ * Four 32-bit counter words and two key words; each round multiplies words
+ * 0 and 2 by the round multipliers, swaps the products' halves into place
+ * and mixes in the key; the key is bumped by the two 32-bit Weyl constants
+ * between rounds.
+ * ==================================================================== */
+static const uint32_t PHILOX32_M0 = 0xD2511F53u;
+static const uint32_t PHILOX32_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX32_W0 = 0x9E3779B9u;  /* golden ratio */
+static const uint32_t PHILOX32_W1 = 0xBB67AE85u;  /* sqrt(3) - 1 */
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += PHILOX32_W0; k1 += PHILOX32_W1; }
+        uint64_t p0 = (uint64_t)PHILOX32_M0 * x0;
+        uint64_t p1 = (uint64_t)PHILOX32_M1 * x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The random actor's draw for player p of env `env_id` at actor step `step`
+ * (R15): word p mod 4 of Philox4x32-10 keyed by the two halves of the actor
+ * seed, counter (step low, step high, env low, env high), with the top bit
+ * of the last word flipped for players 4..7 (env ids stay below 2^63). */
+uint32_t orc_actor_draw(uint64_t seed_act, uint64_t env_id, uint64_t step, int p)
+{
+    uint32_t ctr[4] = { (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)env_id,
+                        (uint32_t)(env_id >> 32) ^ (p >= 4 ? 0x80000000u : 0u) };
+    uint32_t key[2] = { (uint32_t)seed_act, (uint32_t)(seed_act >> 32) };
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[p % 4];
+}
+
 /* Uniform pick in [0, n) from a 32-bit draw: floor(r * n / 2^32). */
 static uint32_t pick(uint32_t r, uint32_t n) { return (uint32_t)(((uint64_t)r * n) >> 32); }
 
@@ -564,9 +607,8 @@ static int legal(const orc_env *s, int p, int cell, int k)
 }
 
 /* Random legal actor (R15): uniform over {pass} + legal (cell, k) listed by
- * cell in row-major order and then k = 1..8.  Player p uses 32-bit draw p of
- * the stream keyed (actor seed, ACTIONS) with counter prefix (env, step, 0):
- * one Philox block serves up to eight players. */
+ * cell in row-major order and then k = 1..8.  Player p uses its actor draw
+ * (orc_actor_draw): one Philox4x32 block serves four players. */
 static void sample_env(const orc_env *s, uint64_t seed_act, uint64_t step_idx, uint64_t env_id, int32_t *actions)
 {
     int32_t L[ORC_MAX_CELLS * 8 + 1];
@@ -577,7 +619,7 @@ static void sample_env(const orc_env *s, uint64_t seed_act, uint64_t step_idx, u
         for (int cell = 0; cell < HW; cell++)
             for (int k = 1; k <= 8; k++)
                 if (legal(s, p, cell, k)) L[n++] = cell * 9 + k;
-        uint32_t r = orc_draw(seed_act, D_ACTIONS, env_id, step_idx, 0, (uint64_t)p);
+        uint32_t r = orc_actor_draw(seed_act, env_id, step_idx, p);
         actions[p] = ((s->alive >> p) & 1) ? L[pick(r, (uint32_t)n)] : 0;
     }
 }
