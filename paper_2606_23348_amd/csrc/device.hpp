@@ -14,7 +14,7 @@ constexpr int kMaxWords = 16;            // 64-bit words of a per-cell bitmap
 
 enum : int { PLAIN = 0, MOUNTAIN = 1, CASTLE = 2, GENERAL = 3 };
 enum : int { MODE_1V1 = 0, MODE_2V2 = 1, MODE_FFA = 2 };
-enum : uint32_t { DOM_MAPGEN = 1, DOM_ACTIONS = 2, DOM_PREGROW = 3 };
+enum : uint32_t { DOM_MAPGEN = 1, DOM_PREGROW = 3 };   // (2 was the actor's, now Philox4x32)
 
 // 32-byte per-env record of the device layout (documented in generals.h).
 struct __align__(16) EnvScalars {
@@ -140,6 +140,40 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64
         x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
         k0 += W0; k1 += W1;
     }
+}
+
+// Philox4x32-10 (same paper): the 32-bit member of the family, one
+// 32x32 -> 64-bit multiply-add per product.
+__device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0, p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0, y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The random actor's block of one env and step (reading R15): lanes 0..31
+// compute the block of players 0..3, lanes 32..63 that of players 4..7 (the
+// counter's top bit flipped), both in the same vector instructions.  Returns
+// this lane's block packed as two 64-bit words: player p's draw is 32-bit
+// half p % 2 (low first) of word (p / 2) % 2 of the block of lane 32 * (p / 4).
+__device__ __forceinline__ void actor_block(uint64_t seed, uint64_t env_id, uint64_t step, uint64_t &w0,
+                                            uint64_t &w1)
+{
+    // the lane-dependent counter word keeps the block on the vector unit
+    uint32_t x0 = (uint32_t)step, x1 = (uint32_t)(step >> 32), x2 = (uint32_t)env_id;
+    uint32_t x3 = (uint32_t)(env_id >> 32) ^ (lane_id() >= 32 ? 0x80000000u : 0u);
+    philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    w0 = (uint64_t)x0 | ((uint64_t)x1 << 32);
+    w1 = (uint64_t)x2 | ((uint64_t)x3 << 32);
 }
 
 // 32-bit draw j of the stream keyed (seed, dom) with counter prefix (c0, c1, c2):

@@ -415,16 +415,15 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
     const uint64_t lf_ok = ((pw << 1) | (pprev >> 63)) & ~cm.col0;   // c - 1 passable, same row
     const uint64_t rt_ok = ((pw >> 1) | (pnext << 63)) & ~cm.colL;   // c + 1 passable, same row
     const uint64_t bw = big[w];
-    // one Philox block per env: player p takes 32-bit draw p.  The identity
-    // shuffle keeps the block on the vector unit: as a wave-uniform value the
-    // compiler would run it on the scalar unit, whose long 64-bit multiply
-    // chains cost more wave time than the vector version.
+    // the actor's draws (reading R15): player p takes 32-bit half p % 2 of
+    // r[p / 2], r0 r1 from the block of players 0..3, r2 r3 from that of 4..7
     uint64_t r0, r1, r2, r3;
     if (blk != nullptr) {                        // computed earlier by the caller (in LDS)
         r0 = blk[0]; r1 = blk[1]; r2 = blk[2]; r3 = blk[3];
     } else {
-        r0 = shfl64(env_id, lane); r1 = step_idx; r2 = 0; r3 = 0;
-        philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
+        uint64_t w0, w1;
+        actor_block(actor_seed, env_id, step_idx, w0, w1);
+        r0 = shfl64(w0, 0); r1 = shfl64(w1, 0); r2 = shfl64(w0, 32); r3 = shfl64(w1, 32);
     }
     for (int p0 = 0; p0 < g.P; p0 += ppr) {
         const int p = p0 + lp;
@@ -642,16 +641,17 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             const uint4 va2 = ga[min(lane + 128, na - 1)];
             const uint4 va3 = ga[min(lane + 192, na - 1)];
             if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
-            // the actor's Philox block does not depend on the state:
-            // computing it while the loads are in flight hides their
-            // latency; it waits in LDS until the actor runs
+            // the actor's Philox blocks do not depend on the state:
+            // computing them while the loads are in flight hides their
+            // latency; they wait in LDS until the actor runs
             if (io.next_actions != nullptr) {
                 const uint64_t tick = (uint64_t)s.tick + ((KIND == K_STEP && io.use_tick) ? 1u : 0u);
-                uint64_t r0 = shfl64(env_id, lane), r1 = io.use_tick ? tick : io.actor_step, r2 = 0, r3 = 0;
-                philox4x64_10(r0, r1, r2, r3, actor_seed, DOM_ACTIONS);
-                if (lane == 0) {
-                    uint64_t *pb = L.gbm + 52;
-                    pb[0] = r0; pb[1] = r1; pb[2] = r2; pb[3] = r3;
+                uint64_t w0, w1;
+                actor_block(actor_seed, env_id, io.use_tick ? tick : io.actor_step, w0, w1);
+                if ((lane & 31) == 0) {
+                    uint64_t *pb = L.gbm + 52 + (lane >> 4);
+                    pb[0] = w0;
+                    pb[1] = w1;
                 }
             }
             if (lane < n16) {
