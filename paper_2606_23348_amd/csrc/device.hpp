@@ -98,6 +98,24 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
     return v;
 }
 
+// Lane i receives v of lane i - 1, lane 0 receives `first` (a DPP wave
+// shift; every lane of the wave must be active).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xF, 0xF, false);
+}
+
+// Raw buffer descriptor of one block of device memory (base in scalar
+// registers, bounds = the block): offsets become scalar or 32-bit vector
+// operands, and an access past the block is dropped by the hardware.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRawWord3 = 0x00020000;      // gfx9-family raw (stride 0) buffer descriptor flags
+
+__device__ __forceinline__ Rsrc buffer_rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawWord3);
+}
+
 // Inclusive prefix sum over the wave (lane order).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {

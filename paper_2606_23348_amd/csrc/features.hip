@@ -33,14 +33,9 @@ __device__ __forceinline__ bool enemy_of(int owner, int p, int mode)
 // block (base in scalar registers, bounds = the block), so a channel or
 // memory-section offset is a scalar operand rather than a 64-bit address
 // per lane, and an access past the block is dropped by the hardware.
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-constexpr int kRawWord3 = 0x00020000;      // gfx9-family raw (stride 0) buffer descriptor flags
 constexpr int kNT = 2;                     // cache policy of the stores: nontemporal
 
-__device__ __forceinline__ Rsrc rsrc(void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawWord3);
-}
+__device__ __forceinline__ Rsrc rsrc(void *base, uint32_t bytes) { return buffer_rsrc(base, bytes); }
 
 __device__ __forceinline__ float age_of(int32_t dt)
 {

@@ -815,46 +815,66 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             }
         }
     } else if (io.obs != nullptr) {
-        // ---- other plane sizes: plane (p, ch) starts m = (8p + ch) * HW mod 4
-        // bytes into a dword.  Lane j computes quad j's code bytes (code_quad);
-        // output dword j of the plane takes the last m bytes of quad j-1 (from
-        // lane j-1 by a shuffle, or carried over from the previous round) and
-        // the first 4-m of quad j.  Dwords that hold bytes of two planes are
-        // left to a byte-wise pass after the loop.
+        // ---- other plane sizes: plane (p, ch) starts m = (8p + ch)·HW mod 4
+        // bytes into a dword.  Channels ch and ch + 4 share m (4·HW is a
+        // multiple of 4), so a player's planes fall into four alignment
+        // classes k = ch mod 4 with m_k = k·HW mod 4 (m_0 = 0).  Lane j
+        // computes quad j's code bytes (code_quad) and army bytes; output
+        // dword j of a plane of class k is the last m_k bytes of quad j-1
+        // (lane j-1's, by a wave shift, or carried over from the previous
+        // round) followed by the first 4-m_k of quad j.  The realignment
+        // moves whole bytes and the channels are bits of a byte, so each
+        // class realigns the code dword once and masks its two channels out
+        // of it.  Dwords that hold bytes of two planes are left to a
+        // byte-wise pass after the loop.
         const int nq = g.HW >> 2;                                   // whole quads
         const int rounds = (nq + 1 + kWave - 1) / kWave;            // quads 0 .. nq
-        uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
+        const Rsrc ro = buffer_rsrc(io.obs, (uint32_t)(g.P * 8 * g.HW));
+        const uint32_t HWu = (uint32_t)g.HW;
+        const uint32_t m1 = HWu & 3u, m2 = (2u * HWu) & 3u, m3 = (3u * HWu) & 3u;
+        const uint32_t M = 0x01010101u;
         for (int p = 0; p < g.P; ++p) {
             const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
-            uint32_t carry[8];
-#pragma unroll
-            for (int ch = 0; ch < 8; ++ch) carry[ch] = 0u;
+            const uint32_t pbase = (uint32_t)p * 8u * HWu;         // byte offset of plane (p, 0), a multiple of 8
+            uint32_t carry_c = 0u, carry_a = 0u;
             for (int r = 0; r < rounds; ++r) {
                 const int j = r * kWave + lane;
                 const int qj = j < (g.S >> 2) ? j : 0;              // stays inside the padded row
                 const uint32_t code = code_quad(L, p, ally, qj);
                 const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[qj];
-#pragma unroll
-                for (int ch = 0; ch < 8; ++ch) {
-                    const uint32_t cur = ch < 7 ? (code >> ch) & 0x01010101u : army_visible(ac, code);
-                    uint32_t prev = shfl32(cur, lane - 1);
-                    if (lane == 0) prev = carry[ch];
-                    carry[ch] = (uint32_t)readlane((int)cur, kWave - 1);
-                    const uint32_t B0 = (uint32_t)((p * 8 + ch) * g.HW);
-                    const uint32_t m = B0 & 3u, d0 = B0 >> 2;
-                    // interior: bytes 4j - m .. 4j - m + 3 all inside the plane
-                    const bool interior = (4 * j >= (int)m) && (4 * j + 4 - (int)m <= g.HW);
-                    if (interior) {
-                        // plain (cached) store: the 32-byte sectors at plane
-                        // boundaries are shared by two stores, and the cache
-                        // merges them; nontemporal partial-sector writes
-                        // measured 1.5x slower on these shapes
-                        const uint32_t v = m == 0 ? cur : __builtin_amdgcn_alignbyte(cur, prev, 4u - m);
-                        ob[d0 + j] = v;
-                    }
+                const uint32_t pc = wave_shr1(code, carry_c), pa = wave_shr1(ac, carry_a);
+                carry_c = (uint32_t)readlane((int)code, kWave - 1);
+                carry_a = (uint32_t)readlane((int)ac, kWave - 1);
+                const uint32_t c1 = m1 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m1);
+                const uint32_t c2 = m2 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m2);
+                const uint32_t c3 = m3 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m3);
+                const uint32_t a3 = m3 == 0u ? ac : __builtin_amdgcn_alignbyte(ac, pa, 4u - m3);
+                // interior: bytes 4j - m .. 4j - m + 3 all inside the plane.
+                // Plain (cached) stores: the 32-byte sectors at plane
+                // boundaries are shared by two stores and the cache merges
+                // them; nontemporal partial-sector writes measured 1.5x
+                // slower on these shapes.
+                const int vo = 4 * j;
+                if (vo + 4 <= g.HW) {
+                    __builtin_amdgcn_raw_buffer_store_b32(code & M, ro, vo, (int)(pbase & ~3u), 0);
+                    __builtin_amdgcn_raw_buffer_store_b32((code >> 4) & M, ro, vo, (int)((pbase + 4u * HWu) & ~3u), 0);
+                }
+                if (vo >= (int)m1 && vo + 4 - (int)m1 <= g.HW) {
+                    __builtin_amdgcn_raw_buffer_store_b32((c1 >> 1) & M, ro, vo, (int)((pbase + HWu) & ~3u), 0);
+                    __builtin_amdgcn_raw_buffer_store_b32((c1 >> 5) & M, ro, vo, (int)((pbase + 5u * HWu) & ~3u), 0);
+                }
+                if (vo >= (int)m2 && vo + 4 - (int)m2 <= g.HW) {
+                    __builtin_amdgcn_raw_buffer_store_b32((c2 >> 2) & M, ro, vo, (int)((pbase + 2u * HWu) & ~3u), 0);
+                    __builtin_amdgcn_raw_buffer_store_b32((c2 >> 6) & M, ro, vo, (int)((pbase + 6u * HWu) & ~3u), 0);
+                }
+                if (vo >= (int)m3 && vo + 4 - (int)m3 <= g.HW) {
+                    __builtin_amdgcn_raw_buffer_store_b32((c3 >> 3) & M, ro, vo, (int)((pbase + 3u * HWu) & ~3u), 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(army_visible(a3, c3), ro, vo, (int)((pbase + 7u * HWu) & ~3u),
+                                                          0);
                 }
             }
         }
+        uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
         // the dwords across plane boundaries: at most one per plane start
         const int n_planes = g.P * 8;
         for (int i = 1 + lane; i < n_planes; i += kWave) {
