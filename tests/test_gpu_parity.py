@@ -132,14 +132,17 @@ def test_c1_full_trajectory(gen):
 
 
 @pytest.mark.parametrize("H,W,mode,P,E,steps", [
-    (24, 24, 0, 2, 48, 300),     # 16-byte aligned planes
-    (10, 10, 1, 4, 40, 300),     # 2v2, 4-byte aligned planes
-    (25, 25, 2, 8, 24, 200),     # FFA-8, unaligned planes, 16-byte chunks
-    (7, 9, 2, 3, 37, 300),       # FFA-3, unaligned planes, 8-byte chunks
+    (24, 24, 0, 2, 48, 300),     # planes of a multiple of 4 cells
+    (10, 10, 1, 4, 40, 300),     # 2v2, planes of a multiple of 4 cells
+    (25, 25, 2, 8, 24, 200),     # FFA-8, H*W = 1 mod 4 over three rounds of quads
+    (7, 9, 2, 3, 37, 300),       # FFA-3, H*W = 3 mod 4 in one round
     (3, 3, 0, 2, 64, 200),       # tiny grid
     (32, 32, 2, 4, 8, 150),      # largest grid
     (11, 23, 1, 4, 30, 250),
     (17, 6, 2, 6, 30, 250),
+    (17, 18, 0, 2, 24, 150),     # H*W = 2 mod 4 over two rounds of quads
+    (19, 17, 2, 5, 20, 150),     # H*W = 3 mod 4 over two rounds; players 4.. draw from the second block
+    (31, 31, 1, 4, 8, 100),      # H*W = 1 mod 4 over four rounds, 2v2
 ])
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
