@@ -177,9 +177,11 @@ int gen_reset(uint64_t seed, uint64_t env_base, int32_t n_envs, int32_t H, int32
 int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int32_t *d_rewards,
              uint8_t *d_dones, int32_t *d_land, int64_t *d_army, void *stream);
 
-/* Random legal actor: for every env, one Philox4x64-10 block with key
- * (actor_seed, 2) and counter (env_base + e, step_idx, 0, 0); player p takes
- * its 32-bit word p (64-bit word p / 2, low half for even p) and picks
+/* Random legal actor (the benchmark driver; the paper fixes no generator):
+ * for every env, player p takes 32-bit word p mod 4 of the Philox4x32-10
+ * block with key (actor_seed low, actor_seed high) and counter (step_idx
+ * low, step_idx high, env low, env high), env = env_base + e, the counter's
+ * top bit flipped for players 4..7 (env ids below 2^63), and picks
  * uniformly, floor(word * n / 2^32), among the n entries of [pass] + the
  * legal (cell, k) moves listed by cell in row-major order, then k = 1..8.
  * Dead players pass.  d_actions int32 [E][P]. */

@@ -1,5 +1,5 @@
 // device.hpp -- gfx950 device helpers for the batched Generals.io step:
-// Philox4x64-10, wave64 primitives, SWAR byte tests, per-launch geometry.
+// Philox4x64-10 (map generator) and 4x32-10 (actor), wave64 primitives, SWAR byte tests, per-launch geometry.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,7 +14,7 @@ constexpr int kMaxWords = 16;            // 64-bit words of a per-cell bitmap
 
 enum : int { PLAIN = 0, MOUNTAIN = 1, CASTLE = 2, GENERAL = 3 };
 enum : int { MODE_1V1 = 0, MODE_2V2 = 1, MODE_FFA = 2 };
-enum : uint32_t { DOM_MAPGEN = 1, DOM_PREGROW = 3 };   // (2 was the actor's, now Philox4x32)
+enum : uint32_t { DOM_MAPGEN = 1, DOM_PREGROW = 3 };   // key words of the generator's streams
 
 // 32-byte per-env record of the device layout (documented in generals.h).
 struct __align__(16) EnvScalars {

@@ -398,7 +398,8 @@ __device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_
 // shifted passable bitmap.  A cell with d legal directions contributes 2d
 // entries (all-but-one, then half) to the list [pass, (cell, k)...]; the
 // uniform pick is located by a prefix over words and a binary search over
-// the bits of one word.  own: [P][16] words, pass/big: [16] words in LDS.
+// the bits of one word.  own: [P][16] words, pass/big: [16] words in LDS;
+// blk: the actor's two Philox4x32 blocks if the caller computed them.
 __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *pass, const uint64_t *big,
                            uint32_t alive, uint64_t actor_seed, uint64_t step_idx, uint64_t env_id, int32_t *act_out,
                            const uint64_t *blk = nullptr)
