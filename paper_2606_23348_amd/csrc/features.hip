@@ -1,8 +1,10 @@
 // features.hip -- the paper's full feature tensor (Appendix A, table of
 // observation channels; reading R17 of this library): 38 float32 maps per
-// player and env, computed by one wave64 per env from the env's state and a
-// per-env memory in HBM (persistent masks, the last enemy sighting per cell,
-// a ring of the last 8 frames).
+// player and env, computed by one workgroup of 1, 2 or 4 wave64s per env
+// from the env's state and a per-env memory in HBM (persistent masks, the
+// last enemy sighting per cell, a ring of the last 8 frames).  Small batches
+// (a training rollout's 512 envs) cannot fill the GPU with one wave per env,
+// so their cells are spread over more waves.
 //
 // Memory traffic dominates (the output alone is 152 bytes per cell and
 // player), so the kernel keeps every store coalesced: lane i of a round
@@ -48,17 +50,20 @@ __device__ __forceinline__ float age_of(int32_t dt)
 // so their stores can be nontemporal; otherwise two stores share the sector
 // at each plane boundary and plain stores let the cache merge them.
 template <bool NT>
-__global__ __launch_bounds__(64) void k_features(FeatArgs a)
+__global__ __launch_bounds__(256) void k_features(FeatArgs a)
 {
     constexpr int kOut = NT ? kNT : 0;        // cache policy of the feature and token stores
     extern __shared__ __align__(16) uint8_t smem[];
     const int e = blockIdx.x, lane = lane_id();
+    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;   // nt = 64 x (waves per env)
+    const bool wave0 = readfirst(tid >> 6) == 0;
     const Geom g = a.g;
     const FeatBlock fb = a.blk;
     const int S = g.S, HW = g.HW, P = g.P;
 
     // LDS: owner [S] | type [S] | army int32 [S] | obm [P][16] | vis [P][16] |
-    //      enemy army total [P] int64 | enemy land [P] int32
+    //      enemy army total [P] int64 | enemy land [P] int32 |
+    //      army total [P] int64 | land [P] int32
     int8_t *Lo = reinterpret_cast<int8_t *>(smem);
     uint8_t *Lt = smem + S;
     int32_t *La = reinterpret_cast<int32_t *>(smem + 2 * S);
@@ -66,6 +71,8 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
     uint64_t *vis = obm + P * 16;
     int64_t *opp_army_l = reinterpret_cast<int64_t *>(vis + P * 16);
     int32_t *opp_land_l = reinterpret_cast<int32_t *>(opp_army_l + P);
+    int64_t *armt_l = reinterpret_cast<int64_t *>(smem + 6 * S + 2 * P * 16 * 8 + 16 * P);
+    int32_t *land_l = reinterpret_cast<int32_t *>(armt_l + P);
 
     const EnvScalars s = a.sc[e];
     {
@@ -74,19 +81,31 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         const uint4 *gt = reinterpret_cast<const uint4 *>(a.type + cell0);
         const uint4 *ga = reinterpret_cast<const uint4 *>(a.army + cell0);
         const int n16 = S >> 4;
-        for (int i = lane; i < n16; i += kWave) {
+        for (int i = tid; i < n16; i += nt) {
             reinterpret_cast<uint4 *>(Lo)[i] = go[i];
             reinterpret_cast<uint4 *>(Lt)[i] = gt[i];
         }
-        for (int i = lane; i < 4 * n16; i += kWave) reinterpret_cast<uint4 *>(La)[i] = ga[i];
+        for (int i = tid; i < 4 * n16; i += nt) reinterpret_cast<uint4 *>(La)[i] = ga[i];
     }
-    wave_sync();
+    // the memory header is read by every wave before the first barrier (the
+    // last barrier orders its rewrite after all of them)
+    uint8_t *blk = a.mem + (size_t)e * fb.bytes;
+    uint32_t *hdr = reinterpret_cast<uint32_t *>(blk);
+    const int32_t t = s.turn;
+    const int slot = t & 7;
+    const bool fresh = readfirst((int)hdr[0]) != (int)kFeatMagic || (uint32_t)readfirst((int)hdr[1]) != s.episode;
+    int32_t stamp[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) stamp[j] = fresh ? -1 : readfirst((int)hdr[2 + j]);
+    __syncthreads();
 
-    // owned-cell bitmaps, team vision, land and army totals
+    // owned-cell bitmaps, team vision, land and army totals (wave 0; the
+    // others wait at the barrier)
     int land[kMaxP];
     int64_t armt[kMaxP];
 #pragma unroll
     for (int p = 0; p < kMaxP; ++p) { land[p] = 0; armt[p] = 0; }
+    if (wave0) {
     for (int w = 0; w < g.NW; ++w) {
         const int c = w * 64 + lane;
         const int o = c < HW ? (int)Lo[c] : -1;
@@ -113,7 +132,8 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         }
     }
     // the enemies' totals of each player, kept in LDS for the scoreboard ring
-    // (scalar registers are scarce across the cell loop)
+    // (scalar registers are scarce across the cell loop), and the players'
+    // own totals for the other waves
     if (lane < P) {
         int32_t ol = 0;
         int64_t oa = 0;
@@ -126,18 +146,25 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         }
         opp_army_l[lane] = oa;
         opp_land_l[lane] = ol;
+#pragma unroll
+        for (int q = 0; q < kMaxP; ++q)
+            if (q == lane) { armt_l[lane] = armt[q]; land_l[lane] = land[q]; }
     }
-    wave_sync();
+    }
+    __syncthreads();
+    if (!wave0) {
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p) {
+            if (p < P) {
+                land[p] = readfirst(land_l[p]);
+                const uint64_t at = (uint64_t)armt_l[p];
+                armt[p] = (int64_t)(((uint64_t)(uint32_t)readfirst((int)(at >> 32)) << 32) |
+                                    (uint32_t)readfirst((int)(uint32_t)at));
+            }
+        }
+    }
 
     // memory header: a block of another episode (or never used) starts empty
-    uint8_t *blk = a.mem + (size_t)e * fb.bytes;
-    uint32_t *hdr = reinterpret_cast<uint32_t *>(blk);
-    const int32_t t = s.turn;
-    const int slot = t & 7;
-    const bool fresh = readfirst((int)hdr[0]) != (int)kFeatMagic || (uint32_t)readfirst((int)hdr[1]) != s.episode;
-    int32_t stamp[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) stamp[j] = fresh ? -1 : readfirst((int)hdr[2 + j]);
     uint32_t hv = 0;                  // bit k: the frame of turn t - k is in the ring
 #pragma unroll
     for (int k = 1; k <= kHist; ++k) {
@@ -150,7 +177,7 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
 
     const Rsrc rm = rsrc(blk, fb.bytes);
     const Rsrc rf = rsrc(fe, (uint32_t)(P * kFeatC * HW * 4));
-    for (int c = lane; c < HW; c += kWave) {
+    for (int c = tid; c < HW; c += nt) {
         const int o = Lo[c], ty = Lt[c];
         const int32_t av = La[c];
         const int w = c >> 6, b = c & 63;
@@ -263,20 +290,20 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
     // scoreboard ring (Section V-A: the two temporal tokens): this turn's
     // enemy totals per player, then the 512-turn windows if asked for
     const int ts = t & (kTokenWindow - 1);
-    for (int j = lane; j < kTokenWindow; j += kWave) {
+    for (int j = tid; j < kTokenWindow; j += nt) {
         if (fresh || j == ts)
             __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(j == ts ? t : -1), rm, 4 * j, (int)fb.tstamp, 0);
     }
-    if (lane < P) {
-        const int64_t oa = opp_army_l[lane];
-        const int off = lane * kTokenWindow + ts;
+    if (tid < P) {
+        const int64_t oa = opp_army_l[tid];
+        const int off = tid * kTokenWindow + ts;
         const u32x2 oav = {(uint32_t)(uint64_t)oa, (uint32_t)((uint64_t)oa >> 32)};
         __builtin_amdgcn_raw_buffer_store_b64(oav, rm, 8 * off, (int)fb.tarmy, 0);
-        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)opp_land_l[lane], rm, 4 * off, (int)fb.tland, 0);
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)opp_land_l[tid], rm, 4 * off, (int)fb.tland, 0);
     }
     if (a.tokens != nullptr) {
         const Rsrc rt = rsrc(a.tokens + (size_t)e * P * 2 * kTokenWindow, (uint32_t)(P * 2 * kTokenWindow * 4));
-        for (int j = lane; j < kTokenWindow; j += kWave) {
+        for (int j = tid; j < kTokenWindow; j += nt) {
             const int32_t tau = t - (kTokenWindow - 1) + j;
             const int sl = tau & (kTokenWindow - 1);
             const bool now = j == kTokenWindow - 1;          // this turn: from registers
@@ -303,7 +330,8 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
         }
     }
 
-    if (lane == 0) {
+    __syncthreads();
+    if (tid == 0) {
         hdr[0] = kFeatMagic;
         hdr[1] = s.episode;
 #pragma unroll
@@ -313,11 +341,13 @@ __global__ __launch_bounds__(64) void k_features(FeatArgs a)
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)
 {
-    const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8 + 12 * a.g.P);
+    const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8 + 28 * a.g.P);
+    // waves per env: enough waves in flight for small batches
+    const int nwv = n_envs <= 2048 ? 4 : n_envs <= 4096 ? 2 : 1;
     if (a.g.HW % 8 == 0)
-        hipLaunchKernelGGL(k_features<true>, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
+        hipLaunchKernelGGL(k_features<true>, dim3((unsigned)n_envs), dim3(kWave * nwv), lds, stream, a);
     else
-        hipLaunchKernelGGL(k_features<false>, dim3((unsigned)n_envs), dim3(kWave), lds, stream, a);
+        hipLaunchKernelGGL(k_features<false>, dim3((unsigned)n_envs), dim3(kWave * nwv), lds, stream, a);
     return hipGetLastError();
 }
 
