@@ -96,6 +96,19 @@ def test_features_trajectory(gen, H, W, mode, P, E, steps):
     run_case(gen, H, W, mode, P, E, steps, seed=H * 31 + W, actor_seed=5, prm=prm_for(H, W), repeat_at=(0, 7, 40))
 
 
+@pytest.mark.parametrize("E,H,W,mode,P", [
+    (1024, 24, 23, 0, 2),        # 8 waves per env, 552 cells: a ragged second round of 512
+    (1500, 16, 17, 1, 4),        # 4 waves, 272 cells over rounds of 256
+    (3000, 13, 11, 0, 2),        # 2 waves, 143 cells over rounds of 128
+    (4097, 9, 7, 1, 4),          # 1 wave
+])
+def test_features_waves_per_env(gen, E, H, W, mode, P):
+    """Batches of at most 1,024 / 2,048 / 4,096 envs spread each env's cells
+    over 8 / 4 / 2 waves, larger ones use one: every split against the
+    oracle."""
+    run_case(gen, H, W, mode, P, E, 12, seed=E, actor_seed=3, prm=prm_for(H, W), record_every=4)
+
+
 def test_features_skipped_recordings(gen):
     """Features recorded every third step on both sides: the turns in between
     are empty boards in the delta stacks."""
