@@ -110,7 +110,7 @@ __global__ __launch_bounds__(512) void k_features(FeatArgs a)
         const int c = w * 64 + lane;
         const int o = c < HW ? (int)Lo[c] : -1;
         for (int p = 0; p < P; ++p) {
-            const uint64_t m = ballot(o == p);
+            const uint64_t m = ballot(o == readfirst(p));
             if (lane == 0) obm[p * 16 + w] = m;
         }
         if (o >= 0) {

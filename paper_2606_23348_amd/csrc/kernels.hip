@@ -771,17 +771,22 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
 
     // ---- per-player owned-cell bitmaps (one ballot per player per 64 cells);
     // with the fused actor also the passable and army > 1 bitmaps
+    // The reads of cells past the map (c >= H*W, up to 63 bytes past a row)
+    // stay inside the env's LDS block; a scalar mask drops their bits.
     for (int w = 0; w < g.NW; ++w) {
         const int c = w * 64 + lane;
-        const bool real = c < g.HW;
-        const int o = real ? (int)L.owner[c] : -1;
+        const int rem = g.HW - 64 * w;
+        const uint64_t real = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
+        const int o = L.owner[c];
         for (int p = 0; p < g.P; ++p) {
-            const uint64_t m = ballot(o == p);
+            // (the player index as an opaque scalar: one compare per ballot
+            // rather than a strength-reduced running difference)
+            const uint64_t m = ballot(o == readfirst(p)) & real;
             if (lane == 0) L.obm[p * 16 + w] = m;
         }
         if (ACT) {
-            const uint64_t pm = ballot(real && L.type[c] != MOUNTAIN);
-            const uint64_t bm = ballot(real && L.armyc[c] > 1);
+            const uint64_t pm = ballot(L.type[c] != MOUNTAIN) & real;
+            const uint64_t bm = ballot(L.armyc[c] > 1) & real;
             if (lane == 0) { L.gbm[w] = pm; L.gbm[16 + w] = bm; }
         }
     }
@@ -1032,7 +1037,7 @@ __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
         const int o = real ? (int)L.owner[c] : -1;
         const bool many = real && a.army[cell0 + c] > 1;
         for (int p = 0; p < g.P; ++p) {
-            const uint64_t m = ballot(o == p);
+            const uint64_t m = ballot(o == readfirst(p));
             if (lane == 0) L.obm[p * 16 + w] = m;
         }
         const uint64_t pm = ballot(real && L.type[c] != MOUNTAIN);
