@@ -222,8 +222,6 @@ __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t b)
 // Bits 0..3 of v to 0x01 in bytes 0..3.
 __device__ __forceinline__ uint32_t spread4(uint32_t v) { return (v * 0x00204081u) & 0x01010101u; }
 
-__device__ __forceinline__ int32_t sat_inc(int32_t a) { return a + (a != INT32_MAX ? 1 : 0); }
-
 __device__ __forceinline__ int32_t sat_add(int32_t a, int32_t b)
 {
     const int64_t s = (int64_t)a + (int64_t)b;

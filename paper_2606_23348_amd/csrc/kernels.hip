@@ -712,7 +712,6 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     }
 
     // ---- growth (Section IV-C), state store, army clamp, scoreboard
-    const bool grow = grow2 || grow50;
     int land_acc[kMaxP];
     int64_t army_acc[kMaxP];
     if (SB) {
@@ -729,12 +728,16 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             const uint32_t t4 = reinterpret_cast<const uint32_t *>(L.type)[q];
             int4 a4 = reinterpret_cast<const int4 *>(L.army)[q];
             int32_t av[4] = {a4.x, a4.y, a4.z, a4.w};
+            // one 0x01 per growing cell byte, without branches: owned (the
+            // owner byte's sign bit clear) and a castle or general (type bit
+            // 1) on even turns or plain (type 0) on multiples of 50; the
+            // army never wraps (saturating add, reading R12)
+            const uint32_t gm2 = grow2 ? 0x01010101u : 0u, gm50 = grow50 ? 0x01010101u : 0u;
+            const uint32_t inc = (~o4 >> 7) & (((t4 >> 1) & gm2) | (~(t4 | (t4 >> 1)) & gm50));
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int o = (int8_t)(o4 >> (8 * k));
-                const uint32_t t = (t4 >> (8 * k)) & 0xFFu;
-                if (grow && o >= 0 && ((grow2 && t >= (uint32_t)CASTLE) || (grow50 && t == (uint32_t)PLAIN)))
-                    av[k] = sat_inc(av[k]);
+                av[k] = __builtin_elementwise_add_sat(av[k], (int32_t)((inc >> (8 * k)) & 1u));
                 if (SB) {
 #pragma unroll
                     for (int p = 0; p < kMaxP; ++p) {
