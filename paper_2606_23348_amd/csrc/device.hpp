@@ -110,6 +110,7 @@ __device__ __forceinline__ uint32_t wave_shr1(uint32_t v, uint32_t first)
 // operands, and an access past the block is dropped by the hardware.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRawWord3 = 0x00020000;      // gfx9-family raw (stride 0) buffer descriptor flags
+constexpr int kAuxNT = 2;                  // buffer store cache policy: nontemporal
 
 __device__ __forceinline__ Rsrc buffer_rsrc(void *base, uint32_t bytes)
 {

@@ -35,7 +35,7 @@ __device__ __forceinline__ bool enemy_of(int owner, int p, int mode)
 // block (base in scalar registers, bounds = the block), so a channel or
 // memory-section offset is a scalar operand rather than a 64-bit address
 // per lane, and an access past the block is dropped by the hardware.
-constexpr int kNT = 2;                     // cache policy of the stores: nontemporal
+constexpr int kNT = kAuxNT;                // cache policy of the stores: nontemporal
 
 __device__ __forceinline__ Rsrc rsrc(void *base, uint32_t bytes) { return buffer_rsrc(base, bytes); }
 

@@ -524,15 +524,17 @@ __device__ __forceinline__ void quad_planes(const Lds &L, const QuadCells &c, ui
 
 // Quad q's dwords of player p's eight planes into the env's observation
 // block ([P][8][HW] bytes), nontemporal.
-__device__ __forceinline__ void quad_store(const Lds &L, const Geom &g, uint8_t *obs, const QuadCells &qc, uint32_t ac,
-                                           int p, int q)
+// ro: buffer descriptor of the env's block; the plane offset is a scalar
+// operand and 4q the one vector offset of all eight stores.
+__device__ __forceinline__ void quad_store(const Lds &L, const Geom &g, const Rsrc &ro, const QuadCells &qc,
+                                           uint32_t ac, int p, int q)
 {
     const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
     uint32_t v[8];
     quad_planes(L, qc, ac, p, ally, q, v);
-    uint8_t *pb = obs + (size_t)p * 8 * g.HW;
 #pragma unroll
-    for (int ch = 0; ch < 8; ++ch) st_nt(reinterpret_cast<uint32_t *>(pb + ch * g.HW) + q, v[ch]);
+    for (int ch = 0; ch < 8; ++ch)
+        __builtin_amdgcn_raw_buffer_store_b32(v[ch], ro, 4 * q, (p * 8 + ch) * g.HW, kAuxNT);
 }
 
 // Code bytes of the four cells of quad q for player p (bit k = channel k,
@@ -811,16 +813,17 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             // bits decoded once for all players) in the plain batch kernels,
             // players outer in the mixed-shape pool, where it was faster.
             const int nq = g.HW >> 2;
+            const Rsrc ro = buffer_rsrc(io.obs, (uint32_t)(g.P * 8 * g.HW));
             if (OBSV == OBS_QUAD) {
                 for (int q = lane; q < nq; q += kWave) {
                     const QuadCells qc = quad_cells(L, q);
                     const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[q];
-                    for (int p = 0; p < g.P; ++p) quad_store(L, g, io.obs, qc, ac, p, q);
+                    for (int p = 0; p < g.P; ++p) quad_store(L, g, ro, qc, ac, p, q);
                 }
             } else {
                 for (int p = 0; p < g.P; ++p)
                     for (int q = lane; q < nq; q += kWave)
-                        quad_store(L, g, io.obs, quad_cells(L, q), reinterpret_cast<const uint32_t *>(L.armyc)[q], p, q);
+                        quad_store(L, g, ro, quad_cells(L, q), reinterpret_cast<const uint32_t *>(L.armyc)[q], p, q);
             }
         }
     } else if (io.obs != nullptr) {
