@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -50,10 +51,16 @@ def log(msg: str):
 
 
 def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel sources with their
+    comments and white space removed: an edit to either leaves the kernels,
+    and so the stored counter readings, as they were."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)     # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                    # line comments
+        h.update(re.sub(r"\s+", "", src).encode())
     return h.hexdigest()[:16]
 
 

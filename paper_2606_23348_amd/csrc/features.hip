@@ -106,50 +106,50 @@ __global__ __launch_bounds__(512) void k_features(FeatArgs a)
 #pragma unroll
     for (int p = 0; p < kMaxP; ++p) { land[p] = 0; armt[p] = 0; }
     if (wave0) {
-    for (int w = 0; w < g.NW; ++w) {
-        const int c = w * 64 + lane;
-        const int o = c < HW ? (int)Lo[c] : -1;
-        for (int p = 0; p < P; ++p) {
-            const uint64_t m = ballot(o == readfirst(p));
-            if (lane == 0) obm[p * 16 + w] = m;
-        }
-        if (o >= 0) {
-            const int32_t av = La[c];
+        for (int w = 0; w < g.NW; ++w) {
+            const int c = w * 64 + lane;
+            const int o = c < HW ? (int)Lo[c] : -1;
+            for (int p = 0; p < P; ++p) {
+                const uint64_t m = ballot(o == readfirst(p));
+                if (lane == 0) obm[p * 16 + w] = m;
+            }
+            if (o >= 0) {
+                const int32_t av = La[c];
 #pragma unroll
-            for (int p = 0; p < kMaxP; ++p)
-                if (o == p) { land[p] += 1; armt[p] += av; }
-        }
-    }
-    wave_sync();
-    team_vision(obm, vis, g);
-#pragma unroll
-    for (int p = 0; p < kMaxP; ++p) {
-        if (p < P) {               // wave-uniform totals live in scalar registers
-            land[p] = readfirst((int)wave_sum_u32((uint32_t)land[p]));
-            const uint64_t at = (uint64_t)wave_sum_i64(armt[p]);
-            armt[p] = (int64_t)(((uint64_t)(uint32_t)readfirst((int)(at >> 32)) << 32) |
-                                (uint32_t)readfirst((int)(uint32_t)at));
-        }
-    }
-    // the enemies' totals of each player, kept in LDS for the scoreboard ring
-    // (scalar registers are scarce across the cell loop), and the players'
-    // own totals for the other waves
-    if (lane < P) {
-        int32_t ol = 0;
-        int64_t oa = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxP; ++q) {
-            if (q < P && q != lane && !(g.mode == MODE_2V2 && q == (lane ^ 2))) {
-                ol += land[q];
-                oa += armt[q];
+                for (int p = 0; p < kMaxP; ++p)
+                    if (o == p) { land[p] += 1; armt[p] += av; }
             }
         }
-        opp_army_l[lane] = oa;
-        opp_land_l[lane] = ol;
+        wave_sync();
+        team_vision(obm, vis, g);
 #pragma unroll
-        for (int q = 0; q < kMaxP; ++q)
-            if (q == lane) { armt_l[lane] = armt[q]; land_l[lane] = land[q]; }
-    }
+        for (int p = 0; p < kMaxP; ++p) {
+            if (p < P) {               // wave-uniform totals live in scalar registers
+                land[p] = readfirst((int)wave_sum_u32((uint32_t)land[p]));
+                const uint64_t at = (uint64_t)wave_sum_i64(armt[p]);
+                armt[p] = (int64_t)(((uint64_t)(uint32_t)readfirst((int)(at >> 32)) << 32) |
+                                    (uint32_t)readfirst((int)(uint32_t)at));
+            }
+        }
+        // the enemies' totals of each player, kept in LDS for the scoreboard ring
+        // (scalar registers are scarce across the cell loop), and the players'
+        // own totals for the other waves
+        if (lane < P) {
+            int32_t ol = 0;
+            int64_t oa = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxP; ++q) {
+                if (q < P && q != lane && !(g.mode == MODE_2V2 && q == (lane ^ 2))) {
+                    ol += land[q];
+                    oa += armt[q];
+                }
+            }
+            opp_army_l[lane] = oa;
+            opp_land_l[lane] = ol;
+#pragma unroll
+            for (int q = 0; q < kMaxP; ++q)
+                if (q == lane) { armt_l[lane] = armt[q]; land_l[lane] = land[q]; }
+        }
     }
     __syncthreads();
     if (!wave0) {
