@@ -587,6 +587,61 @@ __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32
     return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
 }
 
+// The unaligned-plane writer's main pass for players p0, p0 + pstep, ...
+// (every lane of the wave; the dwords that hold bytes of two planes are left
+// to the caller's byte-wise pass).
+__device__ __forceinline__ void obs_stream_planes(const Lds &L, const Geom &g, uint8_t *obs, int p0, int pstep)
+{
+    const int lane = lane_id();
+    const int nq = g.HW >> 2;                                   // whole quads
+    const int rounds = (nq + 1 + kWave - 1) / kWave;            // quads 0 .. nq
+    const Rsrc ro = buffer_rsrc(obs, (uint32_t)(g.P * 8 * g.HW));
+    const uint32_t HWu = (uint32_t)g.HW;
+    const uint32_t m1 = HWu & 3u, m2 = (2u * HWu) & 3u, m3 = (3u * HWu) & 3u;
+    const uint32_t M = 0x01010101u;
+    for (int p = p0; p < g.P; p += pstep) {
+        const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
+        const uint32_t pbase = (uint32_t)p * 8u * HWu;         // byte offset of plane (p, 0), a multiple of 8
+        uint32_t carry_c = 0u, carry_a = 0u;
+        for (int r = 0; r < rounds; ++r) {
+            const int j = r * kWave + lane;
+            const int qj = j < (g.S >> 2) ? j : 0;              // stays inside the padded row
+            const uint32_t code = code_quad(L, p, ally, qj);
+            const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[qj];
+            const uint32_t pc = wave_shr1(code, carry_c), pa = wave_shr1(ac, carry_a);
+            carry_c = (uint32_t)readlane((int)code, kWave - 1);
+            carry_a = (uint32_t)readlane((int)ac, kWave - 1);
+            const uint32_t c1 = m1 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m1);
+            const uint32_t c2 = m2 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m2);
+            const uint32_t c3 = m3 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m3);
+            const uint32_t a3 = m3 == 0u ? ac : __builtin_amdgcn_alignbyte(ac, pa, 4u - m3);
+            // interior: bytes 4j - m .. 4j - m + 3 all inside the plane.
+            // Plain (cached) stores: the 32-byte sectors at plane
+            // boundaries are shared by two stores and the cache merges
+            // them; nontemporal partial-sector writes measured 1.5x
+            // slower on these shapes.
+            const int vo = 4 * j;
+            if (vo + 4 <= g.HW) {
+                __builtin_amdgcn_raw_buffer_store_b32(code & M, ro, vo, (int)(pbase & ~3u), 0);
+                __builtin_amdgcn_raw_buffer_store_b32((code >> 4) & M, ro, vo, (int)((pbase + 4u * HWu) & ~3u), 0);
+            }
+            if (vo >= (int)m1 && vo + 4 - (int)m1 <= g.HW) {
+                __builtin_amdgcn_raw_buffer_store_b32((c1 >> 1) & M, ro, vo, (int)((pbase + HWu) & ~3u), 0);
+                __builtin_amdgcn_raw_buffer_store_b32((c1 >> 5) & M, ro, vo, (int)((pbase + 5u * HWu) & ~3u), 0);
+            }
+            if (vo >= (int)m2 && vo + 4 - (int)m2 <= g.HW) {
+                __builtin_amdgcn_raw_buffer_store_b32((c2 >> 2) & M, ro, vo, (int)((pbase + 2u * HWu) & ~3u), 0);
+                __builtin_amdgcn_raw_buffer_store_b32((c2 >> 6) & M, ro, vo, (int)((pbase + 6u * HWu) & ~3u), 0);
+            }
+            if (vo >= (int)m3 && vo + 4 - (int)m3 <= g.HW) {
+                __builtin_amdgcn_raw_buffer_store_b32((c3 >> 3) & M, ro, vo, (int)((pbase + 3u * HWu) & ~3u), 0);
+                __builtin_amdgcn_raw_buffer_store_b32(army_visible(a3, c3), ro, vo, (int)((pbase + 7u * HWu) & ~3u),
+                                                      0);
+            }
+        }
+    }
+}
+
 // Per-env inputs and outputs of one step (pointers into this env's rows).
 struct EnvIO {
     EnvScalars *sc;
@@ -603,6 +658,7 @@ struct EnvIO {
     uint64_t env_id;            // global id (keys every draw)
     uint64_t actor_step;        // actor step index when the tick is not used
     bool use_tick;              // keep the per-env step counter; the actor draws with it
+    int nwv = 1;                // waves of the workgroup sharing the unaligned observation planes
 };
 
 // One environment step (or reset / observation) on one wave.  OBSV selects
@@ -800,6 +856,9 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     // ---- fog (Section IV-B, team vision R10)
     team_vision(L.obm, L.vis, g);
     wave_sync();
+    // a second wave of the workgroup (FFA with unaligned planes) waits here
+    // for the state and the vision, then writes every other player's planes
+    if (OBSV == OBS_STREAM && io.nwv > 1) __syncthreads();
 
     // Planes of a multiple of 4 cells: each lane takes 4 cells, computes their
     // bytes of all 8 channel planes in registers and stores them directly
@@ -839,53 +898,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
         // class realigns the code dword once and masks its two channels out
         // of it.  Dwords that hold bytes of two planes are left to a
         // byte-wise pass after the loop.
-        const int nq = g.HW >> 2;                                   // whole quads
-        const int rounds = (nq + 1 + kWave - 1) / kWave;            // quads 0 .. nq
-        const Rsrc ro = buffer_rsrc(io.obs, (uint32_t)(g.P * 8 * g.HW));
-        const uint32_t HWu = (uint32_t)g.HW;
-        const uint32_t m1 = HWu & 3u, m2 = (2u * HWu) & 3u, m3 = (3u * HWu) & 3u;
-        const uint32_t M = 0x01010101u;
-        for (int p = 0; p < g.P; ++p) {
-            const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
-            const uint32_t pbase = (uint32_t)p * 8u * HWu;         // byte offset of plane (p, 0), a multiple of 8
-            uint32_t carry_c = 0u, carry_a = 0u;
-            for (int r = 0; r < rounds; ++r) {
-                const int j = r * kWave + lane;
-                const int qj = j < (g.S >> 2) ? j : 0;              // stays inside the padded row
-                const uint32_t code = code_quad(L, p, ally, qj);
-                const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[qj];
-                const uint32_t pc = wave_shr1(code, carry_c), pa = wave_shr1(ac, carry_a);
-                carry_c = (uint32_t)readlane((int)code, kWave - 1);
-                carry_a = (uint32_t)readlane((int)ac, kWave - 1);
-                const uint32_t c1 = m1 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m1);
-                const uint32_t c2 = m2 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m2);
-                const uint32_t c3 = m3 == 0u ? code : __builtin_amdgcn_alignbyte(code, pc, 4u - m3);
-                const uint32_t a3 = m3 == 0u ? ac : __builtin_amdgcn_alignbyte(ac, pa, 4u - m3);
-                // interior: bytes 4j - m .. 4j - m + 3 all inside the plane.
-                // Plain (cached) stores: the 32-byte sectors at plane
-                // boundaries are shared by two stores and the cache merges
-                // them; nontemporal partial-sector writes measured 1.5x
-                // slower on these shapes.
-                const int vo = 4 * j;
-                if (vo + 4 <= g.HW) {
-                    __builtin_amdgcn_raw_buffer_store_b32(code & M, ro, vo, (int)(pbase & ~3u), 0);
-                    __builtin_amdgcn_raw_buffer_store_b32((code >> 4) & M, ro, vo, (int)((pbase + 4u * HWu) & ~3u), 0);
-                }
-                if (vo >= (int)m1 && vo + 4 - (int)m1 <= g.HW) {
-                    __builtin_amdgcn_raw_buffer_store_b32((c1 >> 1) & M, ro, vo, (int)((pbase + HWu) & ~3u), 0);
-                    __builtin_amdgcn_raw_buffer_store_b32((c1 >> 5) & M, ro, vo, (int)((pbase + 5u * HWu) & ~3u), 0);
-                }
-                if (vo >= (int)m2 && vo + 4 - (int)m2 <= g.HW) {
-                    __builtin_amdgcn_raw_buffer_store_b32((c2 >> 2) & M, ro, vo, (int)((pbase + 2u * HWu) & ~3u), 0);
-                    __builtin_amdgcn_raw_buffer_store_b32((c2 >> 6) & M, ro, vo, (int)((pbase + 6u * HWu) & ~3u), 0);
-                }
-                if (vo >= (int)m3 && vo + 4 - (int)m3 <= g.HW) {
-                    __builtin_amdgcn_raw_buffer_store_b32((c3 >> 3) & M, ro, vo, (int)((pbase + 3u * HWu) & ~3u), 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(army_visible(a3, c3), ro, vo, (int)((pbase + 7u * HWu) & ~3u),
-                                                          0);
-                }
-            }
-        }
+        obs_stream_planes(L, g, io.obs, 0, io.nwv);
         uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
         // the dwords across plane boundaries: at most one per plane start
         const int n_planes = g.P * 8;
@@ -932,8 +945,10 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
 // The scoreboard kernels would spill vector registers to scratch under that
 // limit, and the other plane sizes measured slower at 25x25; they keep the
 // default.
-template <int KIND, int OBSV, bool SB, bool ACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((SB || OBSV != OBS_QUAD) ? 1 : 8, 8))) void k_env(EnvArgs a)
+// NWV = 2 (steps of FFA boards with unaligned planes): a second wave per env
+// writes every other player's observation planes.
+template <int KIND, int OBSV, bool SB, bool ACT, int NWV>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB || OBSV != OBS_QUAD) ? 1 : 8, 8))) void k_env(EnvArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const int e = blockIdx.x;
@@ -954,6 +969,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((SB || OBSV 
     io.env_id = a.env_base + (uint64_t)e;
     io.actor_step = a.step_idx;
     io.use_tick = false;
+    if (NWV > 1) {
+        static_assert(NWV == 1 || OBSV == OBS_STREAM, "a second wave only shares the unaligned-plane writer");
+        const int wv = readfirst((int)(threadIdx.x >> 6));
+        if (wv > 0) {
+            // exactly one barrier, matching the one wave 0 passes after the vision
+            const Lds L = carve(smem, g);
+            __syncthreads();
+            if (io.obs != nullptr) obs_stream_planes(L, g, io.obs, wv, NWV);
+            return;
+        }
+        io.nwv = NWV;
+    }
     env_body<KIND, OBSV, SB, ACT>(smem, g, a.prm, a.seed, a.actor_seed, io);
 }
 
@@ -1071,8 +1098,21 @@ static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
     const dim3 grid((unsigned)n_envs), block(kWave);
     const uint32_t lds = lds_bytes(a.g);
     switch (obs_variant(a.g)) {
-    case OBS_QUAD: hipLaunchKernelGGL((k_env<KIND, OBS_QUAD, SB, ACT>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_env<KIND, OBS_STREAM, SB, ACT>), grid, block, lds, stream, a); break;
+    case OBS_QUAD: hipLaunchKernelGGL((k_env<KIND, OBS_QUAD, SB, ACT, 1>), grid, block, lds, stream, a); break;
+    default:
+        // steps of boards with more than 4 players and unaligned planes: the
+        // observation (most of the work) is shared by two waves per env when
+        // the batch leaves room for the second wave (measured: FFA-8 25x25
+        // with 16,384 envs 249 -> 226 us; 17x19 with 32,768 envs a little
+        // slower, so larger batches keep one wave)
+        if constexpr (KIND == K_STEP) {
+            if (a.g.P > 4 && a.obs != nullptr && n_envs <= 16384) {
+                hipLaunchKernelGGL((k_env<KIND, OBS_STREAM, SB, ACT, 2>), grid, dim3(2 * kWave), lds, stream, a);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((k_env<KIND, OBS_STREAM, SB, ACT, 1>), grid, block, lds, stream, a);
+        break;
     }
     return hipGetLastError();
 }
