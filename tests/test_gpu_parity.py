@@ -151,6 +151,16 @@ def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
     run_parity(gen, H, W, mode, P, E, steps, seed=H * 7 + W, actor_seed=99, prm=prm, check_every=1, fused=fused)
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_trajectory_many_player_large_batch(gen, fused):
+    """More than 4 players and unaligned planes in a batch above 16,384 envs:
+    the steps keep one wave per env (smaller batches share the observation
+    between two waves, covered by the FFA cases above)."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
+               auto_reset=1)
+    run_parity(gen, 6, 7, 2, 5, 16400, 25, seed=13, actor_seed=14, prm=prm, check_every=5, fused=fused)
+
+
 def test_trajectory_scoreboard_and_no_autoreset(gen):
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
                auto_reset=0)
