@@ -161,6 +161,14 @@ def test_trajectory_many_player_large_batch(gen, fused):
     run_parity(gen, 6, 7, 2, 5, 16400, 25, seed=13, actor_seed=14, prm=prm, check_every=5, fused=fused)
 
 
+def test_trajectory_scoreboard_many_players(gen):
+    """The scoreboard outputs with more than 4 players and unaligned planes
+    (the two-wave step)."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
+               auto_reset=1)
+    run_parity(gen, 7, 9, 2, 6, 40, 150, seed=15, actor_seed=16, prm=prm, scoreboard=True)
+
+
 def test_trajectory_scoreboard_and_no_autoreset(gen):
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=1, cities_max=3, min_general_dist=3,
                auto_reset=0)
