@@ -1,6 +1,6 @@
 // features.hip -- the paper's full feature tensor (Appendix A, table of
 // observation channels; reading R17 of this library): 38 float32 maps per
-// player and env, computed by one workgroup of 1, 2, 4 or 8 wave64s per env
+// player and env, computed by one workgroup of 2, 4 or 8 wave64s per env
 // from the env's state and a per-env memory in HBM (persistent masks, the
 // last enemy sighting per cell, a ring of the last 8 frames).  Small batches
 // (a training rollout's 512 envs) cannot fill the GPU with one wave per env,
@@ -342,8 +342,11 @@ __global__ __launch_bounds__(512) void k_features(FeatArgs a)
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)
 {
     const uint32_t lds = (uint32_t)(6 * a.g.S + 2 * a.g.P * 16 * 8 + 28 * a.g.P);
-    // waves per env: enough waves in flight for small batches
-    const int nwv = n_envs <= 1024 ? 8 : n_envs <= 2048 ? 4 : n_envs <= 4096 ? 2 : 1;
+    // waves per env: 8 for small batches and for more than 4 players (the
+    // cell loop's work grows with P), 2 where 4 would leave a ragged last
+    // round of waves on the chip, else 4 (fewer envs written at once, and
+    // the ring loads of one env's cells overlap across its waves)
+    const int nwv = (n_envs <= 1024 || a.g.P > 4) ? 8 : n_envs <= 2048 ? 2 : 4;
     if (a.g.HW % 8 == 0)
         hipLaunchKernelGGL(k_features<true>, dim3((unsigned)n_envs), dim3(kWave * nwv), lds, stream, a);
     else

@@ -98,14 +98,17 @@ def test_features_trajectory(gen, H, W, mode, P, E, steps):
 
 @pytest.mark.parametrize("E,H,W,mode,P", [
     (1024, 24, 23, 0, 2),        # 8 waves per env, 552 cells: a ragged second round of 512
-    (1500, 16, 17, 1, 4),        # 4 waves, 272 cells over rounds of 256
-    (3000, 13, 11, 0, 2),        # 2 waves, 143 cells over rounds of 128
-    (4097, 9, 7, 1, 4),          # 1 wave
+    (1500, 16, 17, 1, 4),        # 2 waves, 272 cells over rounds of 128
+    (2048, 5, 13, 0, 2),         # 2 waves, 65 cells: the second wave has one
+    (3000, 13, 11, 0, 2),        # 4 waves, 143 cells: the last wave has none
+    (4097, 9, 7, 1, 4),          # 4 waves, 63 cells: only the first has any
+    (2000, 7, 9, 2, 6),          # more than 4 players: 8 waves at any batch size
+    (4100, 10, 10, 2, 8),
 ])
 def test_features_waves_per_env(gen, E, H, W, mode, P):
-    """Batches of at most 1,024 / 2,048 / 4,096 envs spread each env's cells
-    over 8 / 4 / 2 waves, larger ones use one: every split against the
-    oracle."""
+    """Each env's cells are spread over 8 waves for batches of at most 1,024
+    envs or more than 4 players, else over 2 (at most 2,048 envs) or 4:
+    every split, with waves that own no cell, against the oracle."""
     run_case(gen, H, W, mode, P, E, 12, seed=E, actor_seed=3, prm=prm_for(H, W), record_every=4)
 
 
