@@ -587,10 +587,15 @@ __device__ __forceinline__ uint32_t obs_byte(const Lds &L, const Geom &g, uint32
     return ch < 7 ? (cd >> ch) & 1u : (((cd >> 6) & 1u) ? 0u : L.armyc[c]);
 }
 
-// The unaligned-plane writer's main pass for players p0, p0 + pstep, ...
+// Two waves per env: wave 0 writes the planes of players 0 .. obs_split(P) - 1
+// and then runs the actor, wave 1 the rest (3 of 8 and 5 of 8 players
+// balance the two; measured against 4 and 4: FFA-8 25x25 226 -> 217 us).
+__device__ __forceinline__ int obs_split(int P) { return (P * 3) >> 3; }
+
+// The unaligned-plane writer's main pass for players p_begin .. p_end - 1
 // (every lane of the wave; the dwords that hold bytes of two planes are left
 // to the caller's byte-wise pass).
-__device__ __forceinline__ void obs_stream_planes(const Lds &L, const Geom &g, uint8_t *obs, int p0, int pstep)
+__device__ __forceinline__ void obs_stream_planes(const Lds &L, const Geom &g, uint8_t *obs, int p_begin, int p_end)
 {
     const int lane = lane_id();
     const int nq = g.HW >> 2;                                   // whole quads
@@ -599,7 +604,7 @@ __device__ __forceinline__ void obs_stream_planes(const Lds &L, const Geom &g, u
     const uint32_t HWu = (uint32_t)g.HW;
     const uint32_t m1 = HWu & 3u, m2 = (2u * HWu) & 3u, m3 = (3u * HWu) & 3u;
     const uint32_t M = 0x01010101u;
-    for (int p = p0; p < g.P; p += pstep) {
+    for (int p = p_begin; p < p_end; ++p) {
         const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
         const uint32_t pbase = (uint32_t)p * 8u * HWu;         // byte offset of plane (p, 0), a multiple of 8
         uint32_t carry_c = 0u, carry_a = 0u;
@@ -857,7 +862,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     team_vision(L.obm, L.vis, g);
     wave_sync();
     // a second wave of the workgroup (FFA with unaligned planes) waits here
-    // for the state and the vision, then writes every other player's planes
+    // for the state and the vision, then writes the later players' planes
     if (OBSV == OBS_STREAM && io.nwv > 1) __syncthreads();
 
     // Planes of a multiple of 4 cells: each lane takes 4 cells, computes their
@@ -898,7 +903,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
         // class realigns the code dword once and masks its two channels out
         // of it.  Dwords that hold bytes of two planes are left to a
         // byte-wise pass after the loop.
-        obs_stream_planes(L, g, io.obs, 0, io.nwv);
+        obs_stream_planes(L, g, io.obs, 0, io.nwv > 1 ? obs_split(g.P) : g.P);
         uint32_t *ob = reinterpret_cast<uint32_t *>(io.obs);
         // the dwords across plane boundaries: at most one per plane start
         const int n_planes = g.P * 8;
@@ -946,7 +951,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
 // limit, and the other plane sizes measured slower at 25x25; they keep the
 // default.
 // NWV = 2 (steps of FFA boards with unaligned planes): a second wave per env
-// writes every other player's observation planes.
+// writes the observation planes of the players from obs_split(P) on.
 template <int KIND, int OBSV, bool SB, bool ACT, int NWV>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB || OBSV != OBS_QUAD) ? 1 : 8, 8))) void k_env(EnvArgs a)
 {
@@ -976,7 +981,7 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB ||
             // exactly one barrier, matching the one wave 0 passes after the vision
             const Lds L = carve(smem, g);
             __syncthreads();
-            if (io.obs != nullptr) obs_stream_planes(L, g, io.obs, wv, NWV);
+            if (io.obs != nullptr) obs_stream_planes(L, g, io.obs, obs_split(g.P), g.P);
             return;
         }
         io.nwv = NWV;
