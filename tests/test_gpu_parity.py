@@ -143,6 +143,7 @@ def test_c1_full_trajectory(gen):
     (17, 18, 0, 2, 24, 150),     # H*W = 2 mod 4 over two rounds of quads
     (19, 17, 2, 5, 20, 150),     # H*W = 3 mod 4 over two rounds; players 4.. draw from the second block
     (31, 31, 1, 4, 8, 100),      # H*W = 1 mod 4 over four rounds, 2v2
+    (13, 9, 2, 7, 20, 150),      # FFA-7: the two waves of an env write 2 and 5 players' planes
 ])
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
