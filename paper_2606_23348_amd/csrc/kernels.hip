@@ -698,6 +698,10 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             // lane; indexes are clamped rather than the loads predicated:
             // lanes past the end re-read the last chunk and skip the store)
             const int na = 4 * n16;
+            // two-wave envs issue their state loads at raised wave priority,
+            // so a new env's loads are not queued behind older waves' work
+            // (FFA-8 25x25: 216 -> 211 us; one-wave shapes unchanged)
+            if (io.nwv > 1) __builtin_amdgcn_s_setprio(3);
             const uint4 vo = go[min(lane, n16 - 1)];
             const uint4 vt = gt[min(lane, n16 - 1)];
             const uint4 va0 = ga[min(lane, na - 1)];
@@ -705,6 +709,7 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
             const uint4 va2 = ga[min(lane + 128, na - 1)];
             const uint4 va3 = ga[min(lane + 192, na - 1)];
             if (KIND == K_STEP && lane < g.P) act = io.actions[lane];
+            if (io.nwv > 1) __builtin_amdgcn_s_setprio(0);
             // the actor's Philox blocks do not depend on the state:
             // computing them while the loads are in flight hides their
             // latency; they wait in LDS until the actor runs
