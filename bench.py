@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2606_23348_amd/csrc/kernels.hip", "paper_2606_23348_amd/csrc/features.hip",
                   "paper_2606_23348_amd/csrc/device.hpp", "paper_2606_23348_amd/csrc/internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-EXTRAS = ("step_alone", "features", "copy", "rollout", "served", "pool", "served_mix")
+EXTRAS = ("step_alone", "features", "copy", "c3", "rollout", "served", "pool", "served_mix")
 
 
 _T0 = time.perf_counter()
@@ -93,19 +93,23 @@ def traffic_for(wl_name: str, n_launch_frames: int):
     return rec.get("bytes_per_launch")
 
 
-def copy_ceiling_gbs(torch, n_bytes: int = 1 << 30, reps: int = 10) -> float:
-    """Bandwidth of a plain device-to-device copy (read + write bytes / time):
-    the practical streaming ceiling next to the 8 TB/s peak."""
+def copy_ceiling_gbs(gen, torch, n_bytes: int = 1 << 30, reps: int = 20) -> float:
+    """Bandwidth of the library's streaming copy kernel (16-byte nontemporal
+    loads and stores; read + write bytes / time): the practical ceiling of
+    a read-once / write-once stream next to the 8 TB/s peak."""
     src = torch.empty(n_bytes, dtype=torch.uint8, device="cuda").fill_(1)
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        gen.gen_stream_copy(dst, src, stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record()
+    e0.record(stream)
     for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
+        gen.gen_stream_copy(dst, src, stream)
+    e1.record(stream)
     torch.cuda.synchronize()
+    assert torch.equal(dst[:4096], src[:4096])
     gbs = 2 * n_bytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del src, dst
     torch.cuda.empty_cache()
@@ -337,16 +341,73 @@ def run_served_mix(gen, torch, duration_s: float) -> dict:
             "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
 
 
-def cpu_baseline(wl, n_envs: int, n_steps: int) -> dict:
-    import oracle
-    cfg = oracle.Config(H=wl.H, W=wl.W, mode=wl.mode, P=wl.P, seed=wl.seed, **wl.params())
-    st, _ = oracle.reset(cfg, n_envs)
+def run_plain_leg(gen, torch, wl, steps: int, warmup: int) -> dict:
+    """Another plain workload in the headline's form: `warmup` untimed
+    fused launches, then `steps` timed back to back between one pair of HIP
+    events on the launch stream."""
+    b = gen.Batch(wl.n_envs, wl.H, wl.W, wl.mode, gen.make_params(wl.mode, wl.P, **wl.params()), seed=wl.seed)
+    stream = torch.cuda.current_stream()
+    b.sample(wl.actor_seed, 0)
+    for t in range(warmup):
+        b.step_sample(wl.actor_seed, t + 1)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    oracle.run(cfg, st, wl.actor_seed, 0, n_steps)
-    dt = time.perf_counter() - t0
-    return {"value": n_envs * n_steps / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_envs} envs x {n_steps} steps of {wl.name} (sample + step + observe per frame), "
-                      f"{dt:.1f} s on one host thread"}
+    r0.record(stream)
+    for t in range(steps):
+        b.step_sample(wl.actor_seed, warmup + t + 1)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    avg = r0.elapsed_time(r1) / 1e3 / steps
+    by = step_bytes(wl)
+    achieved = by["step"] * wl.n_envs / avg / 1e9
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": wl.name, "steps": steps, "warmup": warmup, "frames_per_s": wl.n_envs * steps / elapsed,
+            "step_kernel_ms_mean": avg * 1e3,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": by["step"],
+                         "traffic": traffic_for(wl.name, wl.n_envs)}}
+
+
+def host_cores() -> int:
+    """Host cores this process may use (the GPU machine grants 16 per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(wl, n_envs: int, n_steps: int) -> dict:
+    """The oracle on the host's cores: one independent shard of n_envs envs
+    per thread (env ids of each shard disjoint, as one process per env
+    shard would run them; the C oracle releases the GIL), all running the
+    whole loop -- random actor, step, observation -- for n_steps steps.  Also
+    one shard alone on one thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+
+    def shard(i, steps):
+        cfg = oracle.Config(H=wl.H, W=wl.W, mode=wl.mode, P=wl.P, seed=wl.seed, env_base=i * n_envs, **wl.params())
+        st, _ = oracle.reset(cfg, n_envs)
+        t0 = time.perf_counter()
+        oracle.run(cfg, st, wl.actor_seed, 0, steps)
+        return time.perf_counter() - t0
+
+    one = shard(0, n_steps)
+    n = host_cores()
+    n_steps_each = max(1, n_steps // 4)
+    with ThreadPoolExecutor(n) as pool:
+        t0 = time.perf_counter()
+        list(pool.map(lambda i: shard(i, n_steps_each), range(n)))
+        wall = time.perf_counter() - t0
+    return {"value": n * n_envs * n_steps_each / wall, "unit": "frames/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} threads x {n_envs} envs x {n_steps_each} steps of {wl.name} (random actor + step + "
+                      f"observation per frame, each thread its own env shard), {wall:.1f} s wall",
+            "one_core": {"value": n_envs * n_steps / one, "unit": "frames/s", "cores": 1,
+                         "sample": f"{n_envs} envs x {n_steps} steps on one thread, {one:.1f} s"}}
 
 
 def main() -> int:
@@ -472,7 +533,10 @@ def main() -> int:
     torch.cuda.empty_cache()
     if "copy" in legs:
         log("copy ceiling")
-        out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(torch)
+        out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(gen, torch)
+    if "c3" in legs:
+        log("FFA-8 leg")
+        out["c3"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W)
     if "rollout" in legs:
         log("rollout leg")
         out["rollout"] = run_rollout(gen, torch)

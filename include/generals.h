@@ -11,7 +11,8 @@
  *  - "d_" pointers are device pointers (HIP device memory) owned by the
  *    caller; "h_" pointers are host memory owned by the caller.  The library
  *    never frees caller memory and allocates no device memory in the plain
- *    entry points.
+ *    entry points (gen_get_envs keeps one staging block of its own per
+ *    device, see there).
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Launches are asynchronous on that stream unless a call says it blocks.
  *    Asynchronous kernel faults surface as GEN_EHIP on a later call.
@@ -341,6 +342,15 @@ int gen_pool_replay(gen_pool *pool, void *stream);
 /* Blocking copy of one env in the public host format (one row of H*W cells). */
 int gen_pool_get_env(const gen_pool *pool, int32_t env, gen_host_state *h, void *stream);
 
+/* Blocking copy of every env of a pool in the public host format, ragged
+ * (for checkpoints and whole-pool parity checks): owner, army and type hold
+ * the envs' H*W cells back to back in env order (env i starts at the sum of
+ * H*W over envs 0 .. i-1); turn, episode, alive and finished hold one entry
+ * per env; gpos holds GEN_MAX_PLAYERS entries per env, -1 past its players.
+ * The caller sizes the arrays; GEN_ENOMEM if the host copy of the state
+ * buffer cannot be allocated. */
+int gen_pool_get_state(const gen_pool *pool, gen_host_state *h, void *stream);
+
 /* ------------------------------------------------------------------------
  * Served form: an environment server with continuous batching.
  * The caller hands the server one device arena; its size is the memory
@@ -423,8 +433,19 @@ int gen_server_drive(gen_server *srv, int32_t n_clients, int32_t groups_per_clie
 
 /* Blocking copy of selected envs only: env h_env_ids[i] (0 <= id < n_envs)
  * goes to row i of each host array, which therefore hold n_ids rows.  For
- * checkpoints of part of a batch and for sampled parity checks. */
+ * checkpoints of part of a batch and for sampled parity checks.  One gather
+ * kernel packs the envs into a device staging block in the host format, then
+ * one copy per field comes down; the staging block is the library's own (one
+ * per device, allocated on first use, grown when a larger gather needs it,
+ * held until the process ends), and calls on one device take turns on it. */
 int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h, void *stream);
+
+/* Measurement helper, not part of the step: copy `bytes` (a multiple of 16)
+ * from d_src to d_dst (both 16-byte aligned device buffers, not overlapping)
+ * with a plain streaming kernel of 16-byte nontemporal loads and stores.
+ * Timed next to the step kernels, it gives the practical HBM ceiling of a
+ * read-once / write-once stream. */
+int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

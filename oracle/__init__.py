@@ -52,7 +52,7 @@ class _Cfg(ctypes.Structure):
                 ("min_general_dist", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
                 ("pregrow", ctypes.c_int32), ("seed", ctypes.c_uint64), ("env_base", ctypes.c_uint64),
                 ("generator", ctypes.c_int32), ("max_general_dist", ctypes.c_int32),
-                ("castle_radius", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("castle_radius", ctypes.c_int32), ("pad", ctypes.c_int32), ("env_ids", ctypes.c_void_p)]
 
 
 class _Batch(ctypes.Structure):
@@ -111,12 +111,18 @@ class Config:
     generator: int = 0            # 0 synthetic (R14), 1 official rules (R18)
     max_general_dist: int = 0     # R18 spawn-distance cap (0: none)
     castle_radius: int = 6        # R18
+    env_ids: np.ndarray | None = None   # uint64 [E]: global id of each env (None: env_base + e)
 
     def _c(self) -> _Cfg:
+        ids = None
+        if self.env_ids is not None:
+            if self.env_ids.dtype != np.uint64 or not self.env_ids.flags["C_CONTIGUOUS"]:
+                raise TypeError("env_ids must be a C-contiguous uint64 array")
+            ids = self.env_ids.ctypes.data
         return _Cfg(self.H, self.W, self.mode, self.P, self.mountain_thresh, self.cities_min,
                     self.cities_max, self.city_army_min, self.city_army_max,
                     self.min_general_dist, self.auto_reset, self.pregrow, self.seed, self.env_base,
-                    self.generator, self.max_general_dist, self.castle_radius, 0)
+                    self.generator, self.max_general_dist, self.castle_radius, 0, ids)
 
 
 def empty_state(cfg: Config, E: int) -> dict:
@@ -149,6 +155,12 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
+def _cfg(cfg: Config, E: int) -> _Cfg:
+    if cfg.env_ids is not None and cfg.env_ids.shape != (E,):
+        raise ValueError(f"env_ids holds {cfg.env_ids.shape} ids for a batch of {E} envs")
+    return cfg._c()
+
+
 def _check(rc: int):
     if rc != 0:
         raise ValueError("oracle rejected the configuration")
@@ -158,7 +170,7 @@ def reset(cfg: Config, E: int):
     """Fresh maps for envs env_base..env_base+E-1.  Returns (state, attempts)."""
     st = empty_state(cfg, E)
     att = np.zeros(E, np.int32)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_reset_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(att)))
     return st, att
 
@@ -169,7 +181,7 @@ def step(cfg: Config, st: dict, actions: np.ndarray):
     actions = np.ascontiguousarray(actions, np.int32).reshape(E, cfg.P)
     rew = np.zeros((E, cfg.P), np.int32)
     done = np.zeros(E, np.uint8)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_step_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(actions), _ptr(rew), _ptr(done)))
     return rew, done
 
@@ -177,7 +189,7 @@ def step(cfg: Config, st: dict, actions: np.ndarray):
 def observe(cfg: Config, st: dict) -> np.ndarray:
     E = st["turn"].shape[0]
     obs = np.zeros((E, cfg.P, 8, cfg.H, cfg.W), np.uint8)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_observe_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(obs)))
     return obs
 
@@ -186,7 +198,7 @@ def scoreboard(cfg: Config, st: dict):
     E = st["turn"].shape[0]
     land = np.zeros((E, cfg.P), np.int32)
     army = np.zeros((E, cfg.P), np.int64)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_scoreboard_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(land), _ptr(army)))
     return land, army
 
@@ -194,7 +206,7 @@ def scoreboard(cfg: Config, st: dict):
 def sample(cfg: Config, st: dict, seed_act: int, step_idx: int) -> np.ndarray:
     E = st["turn"].shape[0]
     act = np.zeros((E, cfg.P), np.int32)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_sample_batch(ctypes.byref(c), E, ctypes.byref(b), seed_act, step_idx, _ptr(act)))
     return act
 
@@ -206,7 +218,7 @@ def run(cfg: Config, st: dict, seed_act: int, step0: int, n_steps: int):
     rew = np.zeros((E, cfg.P), np.int32)
     done = np.zeros(E, np.uint8)
     obs = np.zeros((E, cfg.P, 8, cfg.H, cfg.W), np.uint8)
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_run(ctypes.byref(c), E, ctypes.byref(b), seed_act, step0, n_steps,
                          _ptr(act), _ptr(rew), _ptr(done), _ptr(obs)))
     return act, rew, done, obs
@@ -231,7 +243,7 @@ def features(cfg: Config, st: dict, mem: np.ndarray, tokens: bool = False):
     assert mem.shape[0] == E and mem.flags["C_CONTIGUOUS"]
     out = np.zeros((E, cfg.P, FEAT_CHANNELS, cfg.H, cfg.W), np.float32)
     tok = np.zeros((E, cfg.P, 2, TOKEN_WINDOW), np.float32) if tokens else None
-    c, b = cfg._c(), _batch(st)
+    c, b = _cfg(cfg, E), _batch(st)
     _check(lib().orc_features_batch(ctypes.byref(c), E, ctypes.byref(b), _ptr(mem), _ptr(out),
                                     _ptr(tok) if tokens else None))
     return (out, tok) if tokens else out

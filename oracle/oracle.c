@@ -50,6 +50,8 @@ typedef struct orc_cfg {
     int32_t max_general_dist;      /* R18: cap on the BFS spawn distance (0 = none; curriculum) */
     int32_t castle_radius;         /* R18: a castle within this BFS distance of every general */
     int32_t pad;
+    const uint64_t *env_ids;       /* NULL: env e of a batch has global id env_base + e;
+                                      else env_ids[e] (envs of one shape scattered over a pool) */
 } orc_cfg;
 
 /* Public host-state format: env-major plain arrays. */
@@ -652,6 +654,12 @@ static void store_env(const orc_env *s, const orc_cfg *cfg, orc_batch *b, int e)
     for (int p = 0; p < P; p++) b->gpos[(size_t)e * P + p] = s->gpos[p];
 }
 
+/* Global id of env e of a batch: every random draw of the env is keyed by it. */
+static uint64_t env_id_of(const orc_cfg *cfg, int e)
+{
+    return cfg->env_ids ? cfg->env_ids[e] : cfg->env_base + (uint64_t)e;
+}
+
 static int cfg_ok(const orc_cfg *cfg)
 {
     if (cfg->H < 3 || cfg->W < 3 || cfg->H * cfg->W > ORC_MAX_CELLS) return 0;
@@ -671,7 +679,7 @@ int orc_reset_batch(const orc_cfg *cfg, int32_t E, orc_batch *b, int32_t *attemp
     orc_env s;
     if (!cfg_ok(cfg)) return -1;
     for (int e = 0; e < E; e++) {
-        uint64_t id = cfg->env_base + (uint64_t)e;
+        uint64_t id = env_id_of(cfg, e);
         int a = mapgen(&s, cfg, id, 0);
         pregrow(&s, cfg, id);
         if (attempts) attempts[e] = a;
@@ -688,7 +696,7 @@ int orc_step_batch(const orc_cfg *cfg, int32_t E, orc_batch *b, const int32_t *a
     if (!cfg_ok(cfg)) return -1;
     for (int e = 0; e < E; e++) {
         load_env(&s, cfg, b, e);
-        step_env(&s, cfg, cfg->env_base + (uint64_t)e, actions + (size_t)e * cfg->P,
+        step_env(&s, cfg, env_id_of(cfg, e), actions + (size_t)e * cfg->P,
                  rewards + (size_t)e * cfg->P, done + e);
         store_env(&s, cfg, b, e);
     }
@@ -733,7 +741,7 @@ int orc_sample_batch(const orc_cfg *cfg, int32_t E, const orc_batch *b, uint64_t
     if (!cfg_ok(cfg)) return -1;
     for (int e = 0; e < E; e++) {
         load_env(&s, cfg, b, e);
-        sample_env(&s, seed_act, step_idx, cfg->env_base + (uint64_t)e, actions + (size_t)e * cfg->P);
+        sample_env(&s, seed_act, step_idx, env_id_of(cfg, e), actions + (size_t)e * cfg->P);
     }
     return 0;
 }

@@ -130,6 +130,8 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_pool_capture.argtypes = [vp, i32, vp, u64, vp, vp, vp, vp]
     L.gen_pool_replay.argtypes = [vp, vp]
     L.gen_pool_get_env.argtypes = [vp, i32, P(gen_host_state), vp]
+    L.gen_pool_get_state.argtypes = [vp, P(gen_host_state), vp]
+    L.gen_stream_copy.argtypes = [vp, vp, u64, vp]
     L.gen_server_create.argtypes = [vp, u64, i32, i32, P(vp)]
     L.gen_server_destroy.argtypes = [vp]
     L.gen_server_open.argtypes = [vp, u64, u64, i32, vp, P(gen_params), i32, u64, P(ctypes.c_uint64)]
@@ -145,7 +147,7 @@ def load_library(path: str) -> ctypes.CDLL:
               "gen_observe", "gen_features", "gen_rollout", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
-              "gen_pool_get_env", "gen_server_create", "gen_server_destroy", "gen_server_open",
+              "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_server_create", "gen_server_destroy", "gen_server_open",
               "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
               "gen_server_report", "gen_server_set_batching", "gen_server_drive"):
         getattr(L, f).restype = ctypes.c_int
@@ -297,6 +299,13 @@ def gen_get_envs(st: gen_state, env_ids, stream=None) -> dict:
     hs = _host_struct(h)
     _check(lib().gen_get_envs(ctypes.byref(st), ids.ctypes.data, len(ids), ctypes.byref(hs), _stream(stream)))
     return h
+
+
+def gen_stream_copy(dst, src, stream=None):
+    """Streaming copy of src into dst (same byte size, 16-byte aligned)."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n
+    _check(lib().gen_stream_copy(_ptr(dst), _ptr(src), n, _stream(stream)))
 
 
 def gen_set_state(st: gen_state, h: dict, stream=None):
@@ -464,6 +473,20 @@ class Pool:
         h = _host_arrays(1, HW, int(self.specs["P"][e]))
         hs = _host_struct(h)
         _check(lib().gen_pool_get_env(self.handle, e, ctypes.byref(hs), _stream(stream)))
+        return h
+
+    def get_state(self, stream=None) -> dict:
+        """Every env in the ragged host format: owner/army/type [sum of H*W]
+        (env e's cells from cell_off[e]), per-env scalars, gpos [n, 8]."""
+        HW = self.specs["H"].astype(np.int64) * self.specs["W"].astype(np.int64)
+        n_cells = int(HW.sum())
+        h = {"owner": np.zeros(n_cells, np.int8), "army": np.zeros(n_cells, np.int32),
+             "type": np.zeros(n_cells, np.uint8), "turn": np.zeros(self.n, np.int32),
+             "episode": np.zeros(self.n, np.uint32), "alive": np.zeros(self.n, np.uint8),
+             "finished": np.zeros(self.n, np.uint8), "gpos": np.zeros((self.n, 8), np.int16)}
+        hs = _host_struct(h)
+        _check(lib().gen_pool_get_state(self.handle, ctypes.byref(hs), _stream(stream)))
+        h["cell_off"] = np.concatenate([[0], np.cumsum(HW)[:-1]]).astype(np.int64)
         return h
 
     def digest(self) -> str:

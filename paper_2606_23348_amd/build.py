@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgenerals.so")
-SOURCES = ["kernels.hip", "features.hip", "abi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "features.hip", "transfer.hip", "abi.cpp", "server.cpp"]
 ARCH = os.environ.get("GEN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -126,6 +127,61 @@ int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
     const uintptr_t need = (B % 16 == 0) ? 16 : 8;
     if (!aligned(d_obs, need)) return fail(GEN_EINVAL, "d_obs must be %u-byte aligned", (unsigned)need);
     return GEN_OK;
+}
+
+// The gather's staging buffer per device (gen_get_envs): allocated on first
+// use, grown when a larger gather comes, held until the process ends.
+struct Staging {
+    uint8_t *ptr = nullptr;
+    uint64_t bytes = 0;
+};
+constexpr int kStagingDevices = 64;
+std::mutex g_staging_mu;
+Staging g_staging[kStagingDevices];
+
+int check_gather(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, const gen_host_state *h,
+                 gen::GatherLayout *lay)
+{
+    if (check_state(st) != GEN_OK) return GEN_EINVAL;
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    if (n_ids < 0 || (n_ids > 0 && h_env_ids == nullptr)) return fail(GEN_EINVAL, "bad env id list");
+    for (int32_t i = 0; i < n_ids; ++i)
+        if (h_env_ids[i] < 0 || h_env_ids[i] >= st->n_envs)
+            return fail(GEN_EINVAL, "env id %d outside [0, %d)", h_env_ids[i], st->n_envs);
+    *lay = gen::gather_layout((uint64_t)n_ids, (uint64_t)st->H * st->W, (uint64_t)st->n_players);
+    return GEN_OK;
+}
+
+// Ids up, one gather launch into the staging block `stg`, one copy per field
+// down into the caller's host arrays (blocking on `s`).
+int gather_to_host(const gen_state &st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h,
+                   const gen::GatherLayout &lay, uint8_t *stg, hipStream_t s)
+{
+    const uint64_t n = (uint64_t)n_ids, HW = (uint64_t)st.H * st.W, P = (uint64_t)st.n_players;
+    const gen::EnvArgs ea = env_args(st);
+    gen::GatherArgs a{};
+    a.lay = lay;
+    a.S = st.stride;
+    a.HW = (int32_t)HW;
+    a.P = (int32_t)P;
+    a.sc = ea.sc;
+    a.owner = ea.owner;
+    a.type = ea.type;
+    a.army = ea.army;
+    a.staging = stg;
+    hipError_t e = hipMemcpyAsync(stg + lay.ids, h_env_ids, 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = gen::launch_gather(a, (uint32_t)n, s);
+    const struct { void *dst; uint64_t off, bytes; } part[] = {
+        {h->owner, lay.owner, n * HW}, {h->type, lay.type, n * HW}, {h->army, lay.army, 4 * n * HW},
+        {h->turn, lay.turn, 4 * n}, {h->episode, lay.episode, 4 * n}, {h->alive, lay.alive, n},
+        {h->finished, lay.finished, n}, {h->gpos, lay.gpos, 2 * n * P}};
+    for (const auto &x : part)
+        if (e == hipSuccess) e = hipMemcpyAsync(x.dst, stg + x.off, x.bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "env gather");
+    return ok();
 }
 
 }  // namespace
@@ -483,40 +539,47 @@ int gen_get_state(const gen_state *st, gen_host_state *h, void *stream)
 
 int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h, void *stream)
 {
-    if (check_state(st) != GEN_OK) return GEN_EINVAL;
-    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
-        !h->gpos)
-        return fail(GEN_EINVAL, "host state has a NULL field");
-    if (n_ids < 0 || (n_ids > 0 && h_env_ids == nullptr)) return fail(GEN_EINVAL, "bad env id list");
-    for (int32_t i = 0; i < n_ids; ++i)
-        if (h_env_ids[i] < 0 || h_env_ids[i] >= st->n_envs)
-            return fail(GEN_EINVAL, "env id %d outside [0, %d)", h_env_ids[i], st->n_envs);
-    const int HW = st->H * st->W, S = st->stride, P = st->n_players;
-    const uint8_t *base = static_cast<const uint8_t *>(st->d_buf);
-    std::vector<gen::EnvScalars> sc((size_t)n_ids);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
-    for (int32_t i = 0; i < n_ids && e == hipSuccess; ++i) {
-        const uint64_t id = (uint64_t)h_env_ids[i];
-        e = hipMemcpyAsync(h->owner + (size_t)i * HW, base + st->off_owner + id * S, HW, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->type + (size_t)i * HW, base + st->off_type + id * S, HW, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->army + (size_t)i * HW, base + st->off_army + id * S * 4, (size_t)HW * 4,
-                               hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&sc[i], base + st->off_scalars + id * sizeof(gen::EnvScalars),
-                               sizeof(gen::EnvScalars), hipMemcpyDeviceToHost, s);
+    uint8_t *stg = nullptr;
+    gen::GatherLayout lay{};
+    if (check_gather(st, h_env_ids, n_ids, h, &lay) != GEN_OK) return GEN_EINVAL;
+    if (n_ids == 0) return ok();
+    std::lock_guard<std::mutex> lk(g_staging_mu);      // one gather at a time uses a device's staging
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= kStagingDevices) return fail(GEN_EINVAL, "device %d beyond the staging table", dev);
+    Staging &sg = g_staging[dev];
+    if (sg.bytes < lay.bytes) {
+        if (sg.ptr) {
+            e = hipFree(sg.ptr);
+            sg.ptr = nullptr;
+            sg.bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "staging release");
+        }
+        const uint64_t want = std::max<uint64_t>(lay.bytes, 1ull << 20);
+        e = hipMalloc(reinterpret_cast<void **>(&sg.ptr), want);
+        if (e != hipSuccess) return hip_fail(e, "staging allocation");
+        sg.bytes = want;
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "env download");
-    for (int32_t i = 0; i < n_ids; ++i) {
-        h->turn[i] = sc[i].turn;
-        h->episode[i] = sc[i].episode;
-        h->alive[i] = sc[i].alive;
-        h->finished[i] = sc[i].finished;
-        for (int p = 0; p < P; ++p) h->gpos[(size_t)i * P + p] = sc[i].gpos[p];
-    }
+    stg = sg.ptr;
+    return gather_to_host(*st, h_env_ids, n_ids, h, lay, stg, static_cast<hipStream_t>(stream));
+}
+
+int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream)
+{
+    if (d_dst == nullptr || d_src == nullptr || !aligned(d_dst, 16) || !aligned(d_src, 16) || bytes % 16 != 0)
+        return fail(GEN_EINVAL, "gen_stream_copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    if (bytes == 0) return ok();
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    const uint64_t n16 = bytes / 16;
+    // 8 workgroups of 256 threads per CU: enough loads in flight to cover
+    // HBM latency; the grid strides over larger buffers
+    const uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>((n16 + 255) / 256, (uint64_t)n_cu * 8));
+    e = gen::launch_stream_copy(d_dst, d_src, n16, (uint32_t)want, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
     return ok();
 }
 
@@ -779,6 +842,41 @@ int gen_pool_get_env(const gen_pool *pool, int32_t env, gen_host_state *h, void 
     h->alive[0] = sc.alive;
     h->finished[0] = sc.finished;
     for (int p = 0; p < d.P; ++p) h->gpos[p] = sc.gpos[p];
+    return ok();
+}
+
+int gen_pool_get_state(const gen_pool *pool, gen_host_state *h, void *stream)
+{
+    if (check_bound(pool) != GEN_OK) return GEN_EINVAL;
+    if (h == nullptr || !h->owner || !h->army || !h->type || !h->turn || !h->episode || !h->alive || !h->finished ||
+        !h->gpos)
+        return fail(GEN_EINVAL, "host state has a NULL field");
+    std::vector<uint8_t> buf;
+    try {
+        buf.resize(pool->state_bytes);
+    } catch (const std::bad_alloc &) {
+        return fail(GEN_ENOMEM, "host allocation of %llu bytes failed", (unsigned long long)pool->state_bytes);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(buf.data(), pool->d_state, pool->state_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pool state download");
+    const gen::EnvScalars *sc = reinterpret_cast<const gen::EnvScalars *>(buf.data() + pool->off_scalars);
+    uint64_t cell = 0;   // first cell of env i in the ragged host rows
+    for (int32_t i = 0; i < pool->n; ++i) {
+        const gen::PoolDesc &d = pool->desc[(size_t)i];
+        const size_t HW = (size_t)d.H * d.W;
+        std::memcpy(h->owner + cell, buf.data() + pool->off_owner + d.cell_off, HW);
+        std::memcpy(h->type + cell, buf.data() + pool->off_type + d.cell_off, HW);
+        std::memcpy(h->army + cell, buf.data() + pool->off_army + (uint64_t)d.cell_off * 4, HW * 4);
+        cell += HW;
+        h->turn[i] = sc[i].turn;
+        h->episode[i] = sc[i].episode;
+        h->alive[i] = sc[i].alive;
+        h->finished[i] = sc[i].finished;
+        for (int p = 0; p < GEN_MAX_PLAYERS; ++p)
+            h->gpos[(size_t)i * GEN_MAX_PLAYERS + p] = p < d.P ? sc[i].gpos[p] : (int16_t)-1;
+    }
     return ok();
 }
 

@@ -118,6 +118,29 @@ struct FeatArgs {
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream);
 
+// Staging block of a gather of selected envs (byte offsets; each section is
+// a host-format array of the selected envs, 256-byte aligned):
+//   ids int32 [n] | owner int8 [n][HW] | type uint8 [n][HW] | army int32 [n][HW]
+//   | turn int32 [n] | episode uint32 [n] | alive uint8 [n] | finished uint8 [n]
+//   | gpos int16 [n][P]
+struct GatherLayout {
+    uint64_t ids, owner, type, army, turn, episode, alive, finished, gpos, bytes;
+};
+
+struct GatherArgs {
+    GatherLayout lay;
+    int32_t S, HW, P;
+    const EnvScalars *sc;
+    const int8_t *owner;
+    const uint8_t *type;
+    const int32_t *army;
+    uint8_t *staging;
+};
+
+GatherLayout gather_layout(uint64_t n, uint64_t HW, uint64_t P);
+hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream);
+hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, uint32_t grid, hipStream_t stream);
+
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);
 hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,

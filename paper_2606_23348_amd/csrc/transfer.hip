@@ -1,0 +1,95 @@
+// transfer.hip -- data movement around the step: the gather of selected envs
+// into a staging block laid out as the public host format (one device-to-host
+// copy per field instead of several per env), and a plain streaming copy
+// that measures the practical HBM ceiling next to the step kernels.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace gen {
+
+// ---------------------------------------------------------------- env gather
+// Workgroup i copies env ids[i] of a batch into row i of each section of the
+// staging block (host-format rows of H*W cells, scalars and P general cells
+// per env).  All offsets come from GatherArgs, which the host computed with
+// gather_layout().
+__global__ __launch_bounds__(256) void k_gather_envs(GatherArgs a)
+{
+    const uint32_t i = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    uint8_t *stg = a.staging;
+    const int32_t e = reinterpret_cast<const int32_t *>(stg + a.lay.ids)[i];
+    const size_t src0 = (size_t)e * (size_t)a.S, dst0 = (size_t)i * (size_t)a.HW;
+    int8_t *owner = reinterpret_cast<int8_t *>(stg + a.lay.owner) + dst0;
+    uint8_t *type = stg + a.lay.type + dst0;
+    int32_t *army = reinterpret_cast<int32_t *>(stg + a.lay.army) + dst0;
+    for (uint32_t c = tid; c < (uint32_t)a.HW; c += blockDim.x) {
+        owner[c] = a.owner[src0 + c];
+        type[c] = a.type[src0 + c];
+        army[c] = a.army[src0 + c];
+    }
+    if (tid == 0) {
+        const EnvScalars s = a.sc[e];
+        reinterpret_cast<int32_t *>(stg + a.lay.turn)[i] = s.turn;
+        reinterpret_cast<uint32_t *>(stg + a.lay.episode)[i] = s.episode;
+        (stg + a.lay.alive)[i] = s.alive;
+        (stg + a.lay.finished)[i] = s.finished;
+    }
+    if (tid < (uint32_t)a.P) reinterpret_cast<int16_t *>(stg + a.lay.gpos)[(size_t)i * a.P + tid] = a.sc[e].gpos[tid];
+}
+
+static uint64_t up256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+GatherLayout gather_layout(uint64_t n, uint64_t HW, uint64_t P)
+{
+    GatherLayout L{};
+    uint64_t o = 0;
+    L.ids = o;      o += up256(4 * n);
+    L.owner = o;    o += up256(n * HW);
+    L.type = o;     o += up256(n * HW);
+    L.army = o;     o += up256(4 * n * HW);
+    L.turn = o;     o += up256(4 * n);
+    L.episode = o;  o += up256(4 * n);
+    L.alive = o;    o += up256(n);
+    L.finished = o; o += up256(n);
+    L.gpos = o;     o += up256(2 * n * P);
+    L.bytes = o;
+    return L;
+}
+
+hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_gather_envs, dim3(n_ids), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- streaming copy
+// dst[i] = src[i] over 16-byte elements: each thread moves four 16-byte
+// elements per round (loads first, then stores), nontemporal on both sides,
+// the grid striding over the buffer.  A measurement of the achievable HBM
+// rate for a read-once / write-once stream.
+__global__ __launch_bounds__(256) void k_stream_copy(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
+                                                      uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 v0 = __builtin_nontemporal_load(src + i);
+        const u32x4 v1 = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 v2 = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 v3 = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(v0, dst + i);
+        __builtin_nontemporal_store(v1, dst + i + stride);
+        __builtin_nontemporal_store(v2, dst + i + 2 * stride);
+        __builtin_nontemporal_store(v3, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, stream, static_cast<u32x4 *>(dst),
+                       static_cast<const u32x4 *>(src), n16);
+    return hipGetLastError();
+}
+
+}  // namespace gen

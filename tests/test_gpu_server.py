@@ -79,20 +79,29 @@ def test_server_mix_vs_alone(gen):
                 assert np.array_equal(x[k], y[k])
         for x, y in ((oa, ob), (aa, ab), (ra, rb), (da, db)):
             assert np.array_equal(x, y)
-    # and the same as independent oracle runs (first and last env of every group)
+    # and every env of every group the same as an independent oracle run:
+    # state, observation block, actions, rewards and done
     for i, s in enumerate(specs):
-        for e in {0, len(s["H"]) - 1}:
-            cfg = oracle.Config(H=int(s["H"][e]), W=int(s["W"][e]), mode=int(s["mode"][e]), P=int(s["P"][e]),
+        st_m, obs_m, act_m, rew_m, done_m = results["mixed"][i]
+        at_obs = at_act = 0
+        for e in range(len(s["H"])):
+            H, W, P = int(s["H"][e]), int(s["W"][e]), int(s["P"][e])
+            cfg = oracle.Config(H=H, W=W, mode=int(s["mode"][e]), P=P,
                                 mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=int(s["cities_min"][e]),
                                 cities_max=int(s["cities_max"][e]), city_army_min=40, city_army_max=50,
                                 min_general_dist=int(s["min_general_dist"][e]), auto_reset=1, seed=17,
                                 env_base=int(bases[i]) + e)
             ost, _ = oracle.reset(cfg, 1)
             for t in range(T):
-                oracle.step(cfg, ost, oracle.sample(cfg, ost, 23, t))
-            got = results["mixed"][i][0][e]
+                r, d = oracle.step(cfg, ost, oracle.sample(cfg, ost, 23, t))
             for k in KEYS:
-                assert np.array_equal(got[k], ost[k]), (i, e, k)
+                assert np.array_equal(st_m[e][k], ost[k]), (i, e, k)
+            want = oracle.observe(cfg, ost).reshape(-1)
+            assert np.array_equal(obs_m[at_obs:at_obs + want.size], want), (i, e, "obs")
+            assert np.array_equal(rew_m[at_act:at_act + P], r[0]) and done_m[e] == d[0], (i, e, "reward")
+            assert np.array_equal(act_m[at_act:at_act + P], oracle.sample(cfg, ost, 23, T)[0]), (i, e, "actions")
+            at_obs += want.size
+            at_act += P
 
 
 def test_server_budget_admission(gen):

@@ -447,3 +447,26 @@ def test_capture_invariants_ffa():
                     assert not (st["owner"][e] == v).any()
                     assert st["type"][e, st["gpos"][e, v]] == 2
     assert seen > 20
+
+
+def test_env_ids_key_each_env():
+    """A batch whose envs carry explicit global ids behaves as separate
+    batches of one env at those ids (the pool parity checks group envs of
+    one shape that are scattered over the pool)."""
+    ids = np.array([5, 9, 2, 700], np.uint64)
+    kw = dict(H=7, W=6, mode=2, P=3, cities_min=1, cities_max=3, min_general_dist=3, seed=12, auto_reset=1)
+    grouped = oracle.Config(env_ids=ids, **kw)
+    st, _ = oracle.reset(grouped, len(ids))
+    singles = [(oracle.Config(env_base=int(e), **kw),) for e in ids]
+    sts = [oracle.reset(c[0], 1)[0] for c in singles]
+    for t in range(60):
+        a = oracle.sample(grouped, st, 4, t)
+        r, d = oracle.step(grouped, st, a)
+        for j, (c,) in enumerate(singles):
+            aj = oracle.sample(c, sts[j], 4, t)
+            rj, dj = oracle.step(c, sts[j], aj)
+            assert np.array_equal(a[j], aj[0]) and np.array_equal(r[j], rj[0]) and d[j] == dj[0]
+            for k in st:
+                assert np.array_equal(st[k][j], sts[j][k][0])
+    with pytest.raises(ValueError):
+        oracle.reset(grouped, 3)
