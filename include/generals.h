@@ -440,6 +440,21 @@ int gen_server_drive(gen_server *srv, int32_t n_clients, int32_t groups_per_clie
  * held until the process ends), and calls on one device take turns on it. */
 int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): gen_get_envs with its staging block in
+ * the library's static device array of GEN_STATIC_STAGING_BYTES per device
+ * (8 MiB, held by every device the library runs on until the process ends)
+ * instead of a buffer the library allocates.  It allocates no device memory.
+ * The state must live on the current device (GEN_EINVAL otherwise);
+ * GEN_ENOMEM when the gather needs more than the array holds (n_ids * (6 *
+ * H * W + 10 + 2 * P) bytes plus 256-byte alignment of each of 9 sections).
+ * Every call on one device stages through that device's one array: calls
+ * that overlap on one device race and must be serialised by the caller.
+ * Blocking on `stream`, as gen_get_envs. */
+#define GEN_STATIC_STAGING_BYTES (8u << 20)
+int gen_get_envs_static(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h,
+                        void *stream);
+
 /* Measurement helper, not part of the step: copy `bytes` (a multiple of 16)
  * from d_src to d_dst (both 16-byte aligned device buffers, not overlapping)
  * with a plain streaming kernel of 16-byte nontemporal loads and stores.

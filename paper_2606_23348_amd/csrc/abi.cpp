@@ -151,6 +151,13 @@ int check_gather(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, c
         if (h_env_ids[i] < 0 || h_env_ids[i] >= st->n_envs)
             return fail(GEN_EINVAL, "env id %d outside [0, %d)", h_env_ids[i], st->n_envs);
     *lay = gen::gather_layout((uint64_t)n_ids, (uint64_t)st->H * st->W, (uint64_t)st->n_players);
+    int dev = 0;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipPointerGetAttributes(&attr, st->d_buf);
+    if (e != hipSuccess) return hip_fail(e, "state buffer query");
+    if (attr.device != dev)
+        return fail(GEN_EINVAL, "the state lives on device %d, the current device is %d", attr.device, dev);
     return GEN_OK;
 }
 
@@ -563,6 +570,24 @@ int gen_get_envs(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, g
     }
     stg = sg.ptr;
     return gather_to_host(*st, h_env_ids, n_ids, h, lay, stg, static_cast<hipStream_t>(stream));
+}
+
+int gen_get_envs_static(const gen_state *st, const int32_t *h_env_ids, int32_t n_ids, gen_host_state *h,
+                        void *stream)
+{
+    gen::GatherLayout lay{};
+    if (check_gather(st, h_env_ids, n_ids, h, &lay) != GEN_OK) return GEN_EINVAL;
+    if (lay.bytes > GEN_STATIC_STAGING_BYTES)
+        return fail(GEN_ENOMEM, "a gather of %d envs stages %llu bytes, the static array holds %llu", n_ids,
+                    (unsigned long long)lay.bytes, (unsigned long long)GEN_STATIC_STAGING_BYTES);
+    if (n_ids == 0) return ok();
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    void *stg = nullptr;
+    e = gen::static_staging(dev, &stg);
+    if (e != hipSuccess) return hip_fail(e, "static staging address");
+    return gather_to_host(*st, h_env_ids, n_ids, h, lay, static_cast<uint8_t *>(stg), static_cast<hipStream_t>(stream));
 }
 
 int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream)

@@ -11,6 +11,8 @@
 
 namespace gen {
 
+constexpr int kMaxDevices = 64;     // devices the library keeps per-device state for
+
 struct EnvArgs {
     Geom g;
     GenParamsDev prm;
@@ -139,6 +141,9 @@ struct GatherArgs {
 
 GatherLayout gather_layout(uint64_t n, uint64_t HW, uint64_t P);
 hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream);
+// Device address of the static staging array (GEN_STATIC_STAGING_BYTES) on
+// `device`, which must be the current device; looked up once per device.
+hipError_t static_staging(int device, void **out);
 hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, uint32_t grid, hipStream_t stream);
 
 uint32_t lds_bytes(const Geom &g);

@@ -1,7 +1,10 @@
 // transfer.hip -- data movement around the step: the gather of selected envs
 // into a staging block laid out as the public host format (one device-to-host
-// copy per field instead of several per env), and a plain streaming copy
-// that measures the practical HBM ceiling next to the step kernels.
+// copy per field instead of several per env), the library's static staging
+// array for callers that cannot allocate, and a plain streaming copy that
+// measures the practical HBM ceiling next to the step kernels.
+#include <mutex>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -60,6 +63,34 @@ hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream
 {
     hipLaunchKernelGGL(k_gather_envs, dim3(n_ids), dim3(256), 0, stream, a);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- static staging
+// The staging array of gen_get_envs_static: one copy per GPU, alive until
+// the process ends.  Host code never uses its name as an address (in host
+// code it names a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current, and only
+// that address is passed to kernels and copies.
+static __device__ __align__(256) uint8_t scratch[GEN_STATIC_STAGING_BYTES];
+
+namespace {
+std::mutex g_sym_mu;
+void *g_sym_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_staging(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_sym_mu);
+    if (g_sym_ptr[device] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_sym_ptr[device] = p;
+    }
+    *out = g_sym_ptr[device];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- streaming copy
