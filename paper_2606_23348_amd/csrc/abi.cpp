@@ -452,7 +452,9 @@ int gen_features(const gen_state *st, void *d_mem, uint64_t mem_bytes, float *d_
     a.mem = static_cast<uint8_t *>(d_mem);
     a.feat = d_feat;
     a.tokens = d_tokens;
-    hipError_t e = gen::launch_features(a, st->n_envs, static_cast<hipStream_t>(stream));
+    hipError_t e = gen::feature_tables_ready();
+    if (e != hipSuccess) return hip_fail(e, "feature table upload");
+    e = gen::launch_features(a, st->n_envs, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "features launch");
     return ok();
 }
@@ -473,6 +475,8 @@ int gen_rollout(const gen_state *st, void *d_mem, uint64_t mem_bytes, int32_t n_
     if (mem_bytes < (uint64_t)fb.bytes * (uint64_t)st->n_envs)
         return fail(GEN_ENOMEM, "feature memory holds %llu bytes, the batch needs %llu", (unsigned long long)mem_bytes,
                     (unsigned long long)((uint64_t)fb.bytes * (uint64_t)st->n_envs));
+    hipError_t e = gen::feature_tables_ready();
+    if (e != hipSuccess) return hip_fail(e, "feature table upload");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t E = (size_t)st->n_envs, P = (size_t)st->n_players, HW = (size_t)st->H * st->W;
     const size_t f_stride = E * P * GEN_FEAT_CHANNELS * HW, t_stride = E * P * 2 * GEN_TOKEN_WINDOW;
@@ -488,7 +492,7 @@ int gen_rollout(const gen_state *st, void *d_mem, uint64_t mem_bytes, int32_t n_
     sa.type = base.type;
     sa.army = base.army;
     sa.actions = d_actions;
-    hipError_t e = gen::launch_sample(sa, st->n_envs, s);
+    e = gen::launch_sample(sa, st->n_envs, s);
     if (e != hipSuccess) return hip_fail(e, "rollout sample launch");
     for (int32_t t = 0; t < n_steps; ++t) {
         gen::FeatArgs fa{};

@@ -14,6 +14,10 @@
 // are loaded from the ring before its 24 instantaneous channels are written,
 // so their latency hides behind those stores; the delta stacks then walk the
 // frames for all players with two running values per player.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace gen {
@@ -39,8 +43,19 @@ constexpr int kNT = kAuxNT;                // cache policy of the stores: nontem
 
 __device__ __forceinline__ Rsrc rsrc(void *base, uint32_t bytes) { return buffer_rsrc(base, bytes); }
 
+}  // namespace
+
+// log(1 + dt) / 5 (channel 21) for dt in [0, kAgeTable): filled once per
+// device by host code from the host C library's double log1p, divided by 5
+// in double and rounded once to float32; larger gaps are computed here in
+// double the same way.
+__device__ float g_age_table[kAgeTable];
+
+namespace {
+
 __device__ __forceinline__ float age_of(int32_t dt)
 {
+    if ((uint32_t)dt < (uint32_t)kAgeTable) return g_age_table[dt];
     return (float)(log1p((double)dt) / 5.0);
 }
 
@@ -337,6 +352,27 @@ __global__ __launch_bounds__(512) void k_features(FeatArgs a)
 #pragma unroll
         for (int j = 0; j < 8; ++j) hdr[2 + j] = (uint32_t)(j == slot ? t : stamp[j]);
     }
+}
+
+namespace {
+std::mutex g_age_mu;
+bool g_age_ready[kMaxDevices] = {};
+}  // namespace
+
+hipError_t feature_tables_ready()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_age_mu);
+    if (g_age_ready[dev]) return hipSuccess;
+    std::vector<float> t(kAgeTable);
+    for (int dt = 0; dt < kAgeTable; ++dt) t[(size_t)dt] = (float)(std::log1p((double)dt) / 5.0);
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_age_table), t.data(), t.size() * sizeof(float), 0, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) g_age_ready[dev] = true;
+    return e;
 }
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream)

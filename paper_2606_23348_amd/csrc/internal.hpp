@@ -119,6 +119,11 @@ struct FeatArgs {
 };
 
 hipError_t launch_features(const FeatArgs &a, int n_envs, hipStream_t stream);
+// Entries of the channel-21 table (log(1 + dt) / 5 for dt below this).
+constexpr int kAgeTable = 65536;
+// Upload the feature kernel's tables to the current device once (blocking);
+// called by every entry point that launches the features kernel.
+hipError_t feature_tables_ready();
 
 // Staging block of a gather of selected envs (byte offsets; each section is
 // a host-format array of the selected envs, 256-byte aligned):

@@ -6,10 +6,11 @@ itself is covered by test_gpu_parity) and record features after the reset
 and after the steps the case selects.  The tolerance comes from the
 arithmetic: every channel is an exact integer, a 0/1 mask or a value computed
 in double and rounded once to float32 (15, 22, 23: a division, correctly
-rounded on both sides), so all must match bit for bit -- except channel 21,
-log1p in double, where the device and host math libraries may differ in the
-last double bit and so, rarely, by one float32 ulp after rounding.  The
-tokens are integers converted to float32: bit-exact.
+rounded on both sides) or, for channel 21, log1p in double divided by 5
+and rounded once, which the library takes from a table its host code fills
+with the host C library's log1p (the oracle calls the same function), so
+every channel must match bit for bit.  The tokens are integers converted to
+float32: bit-exact.
 """
 import numpy as np
 import pytest
@@ -31,19 +32,14 @@ def gen():
 
 
 def assert_features_equal(got, want, where):
-    """got, want: float32 [..., 38, H, W]."""
+    """got, want: float32 [..., 38, H, W], compared bit for bit."""
     assert got.shape == want.shape, where
-    g = np.delete(got, AGE, axis=-3)
-    w = np.delete(want, AGE, axis=-3)
+    g, w = got.view(np.int32), want.view(np.int32)
     if not np.array_equal(g, w):
         bad = np.argwhere(g != w)
         idx = tuple(bad[0])
         raise AssertionError(f"{where}: {len(bad)} values differ, first at {bad[:4].tolist()} "
-                             f"(gpu {g[idx]}, oracle {w[idx]}; channel index after dropping {AGE})")
-    ga = got[..., AGE, :, :].view(np.int32).astype(np.int64)
-    wa = want[..., AGE, :, :].view(np.int32).astype(np.int64)
-    ulp = np.abs(ga - wa).max(initial=0)
-    assert ulp <= 1, f"{where}: channel {AGE} off by {ulp} ulp"
+                             f"(gpu {got[idx]}, oracle {want[idx]})")
 
 
 def run_case(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, record_every=1, repeat_at=()):
