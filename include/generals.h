@@ -376,11 +376,20 @@ typedef struct gen_group_buffers {
 } gen_group_buffers;
 
 typedef struct gen_server_stats {
-    uint64_t requests, frames, launches, groups_open, groups_refused;
+    uint64_t requests, frames, launches;
+    uint64_t groups_open;       /* admitted groups */
+    uint64_t groups_queued;     /* opens that had to wait for memory (since the last reset) */
     uint64_t arena_bytes, bytes_in_use;
-    double lat_p50_us, lat_p99_us, lat_mean_us;   /* submit -> completion seen by the server */
+    /* step latency, submit -> completion seen by the server, over the
+     * requests since the last reset: p50 and p99 from a histogram of 32
+     * log-spaced buckets per power of two (within 1.6% of the sample),
+     * mean and max exact */
+    double lat_p50_us, lat_p99_us, lat_mean_us;
     double envs_per_launch;
     double wall_s;              /* gen_server_drive: length of the measured window */
+    uint64_t groups_pending;    /* groups waiting for memory now */
+    uint64_t lat_samples;
+    double lat_max_us;
 } gen_server_stats;
 
 /* d_arena: device buffer of arena_bytes (256-byte aligned) the server may
@@ -390,12 +399,23 @@ int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_stre
                       gen_server **out);
 /* Finishes the work in flight, stops the scheduler, releases host objects. */
 int gen_server_destroy(gen_server *srv);
-/* Admit a group: plan, carve its buffers, generate its maps (blocking).
+/* Open a group: plan it, and if its buffers fit in the arena now (and no
+ * earlier group is waiting), carve them and generate its maps (blocking):
+ * GEN_OK, *group is steppable.  If they do not fit, the group is queued:
+ * GEN_EBUDGET with *group set, and it is admitted (buffers carved, maps
+ * generated) in order of arrival as soon as closes free enough memory; a
+ * group larger than the whole arena is refused with GEN_EINVAL.  Requests
+ * may be submitted to a queued group: they run once it is admitted.
  * actor != 0: every step also draws the group's next actions with the random
  * actor (seed actor_seed, each env's own step counter); else the caller
  * writes actions into the group's action buffer before each request. */
 int gen_server_open(gen_server *srv, uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
                     const gen_params *common, int32_t actor, uint64_t actor_seed, uint64_t *group);
+/* Wait until a queued group is admitted: GEN_OK (at once for an admitted
+ * group), GEN_EBUSY if timeout_us passed first (timeout_us < 0: wait
+ * forever), GEN_ENOTFOUND if it was closed, GEN_EHIP if its admission failed. */
+int gen_server_wait_admitted(gen_server *srv, uint64_t group, int64_t timeout_us);
+/* Buffers of an admitted group (GEN_EBUSY while it is queued). */
 int gen_server_buffers(gen_server *srv, uint64_t group, gen_group_buffers *out);
 /* Queue one step of every env of the group; *ticket identifies it. */
 int gen_server_submit(gen_server *srv, uint64_t group, uint64_t *ticket);
@@ -404,7 +424,9 @@ int gen_server_submit(gen_server *srv, uint64_t group, uint64_t *ticket);
  * GEN_ENOTFOUND for an unknown or already collected ticket. */
 int gen_server_wait(gen_server *srv, uint64_t ticket, int64_t timeout_us);
 /* Waits for the group's work in flight, drops its queued requests (their
- * tickets fail with GEN_ENOTFOUND) and returns its memory to the arena. */
+ * tickets fail with GEN_ENOTFOUND) and returns its memory to the arena,
+ * then admits the queued groups that now fit.  A queued group is simply
+ * taken off the queue. */
 int gen_server_close(gen_server *srv, uint64_t group);
 int gen_server_report(gen_server *srv, gen_server_stats *out, int32_t reset);
 

@@ -77,10 +77,11 @@ class gen_group_buffers(ctypes.Structure):
 
 class gen_server_stats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_uint64), ("frames", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("groups_open", ctypes.c_uint64), ("groups_refused", ctypes.c_uint64),
+                ("groups_open", ctypes.c_uint64), ("groups_queued", ctypes.c_uint64),
                 ("arena_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
                 ("lat_p50_us", ctypes.c_double), ("lat_p99_us", ctypes.c_double), ("lat_mean_us", ctypes.c_double),
-                ("envs_per_launch", ctypes.c_double), ("wall_s", ctypes.c_double)]
+                ("envs_per_launch", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("groups_pending", ctypes.c_uint64), ("lat_samples", ctypes.c_uint64), ("lat_max_us", ctypes.c_double)]
 
 
 _lib = None
@@ -136,6 +137,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_server_create.argtypes = [vp, u64, i32, i32, P(vp)]
     L.gen_server_destroy.argtypes = [vp]
     L.gen_server_open.argtypes = [vp, u64, u64, i32, vp, P(gen_params), i32, u64, P(ctypes.c_uint64)]
+    L.gen_server_wait_admitted.argtypes = [vp, u64, ctypes.c_int64]
     L.gen_server_buffers.argtypes = [vp, u64, P(gen_group_buffers)]
     L.gen_server_submit.argtypes = [vp, u64, P(ctypes.c_uint64)]
     L.gen_server_wait.argtypes = [vp, u64, ctypes.c_int64]
@@ -148,7 +150,7 @@ def load_library(path: str) -> ctypes.CDLL:
               "gen_observe", "gen_features", "gen_rollout", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
-              "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_get_envs_static", "gen_server_create", "gen_server_destroy", "gen_server_open",
+              "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_get_envs_static", "gen_server_create", "gen_server_destroy", "gen_server_open", "gen_server_wait_admitted",
               "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
               "gen_server_report", "gen_server_set_batching", "gen_server_drive"):
         getattr(L, f).restype = ctypes.c_int
@@ -561,13 +563,29 @@ class Server:
         self.close_server()
 
     def open(self, specs: dict, seed: int, env_base: int = 0, common: gen_params | None = None,
-             actor_seed: int | None = None) -> int:
+             actor_seed: int | None = None, queue: bool = False):
+        """Open a group.  queue=False: its id, or GenError(GEN_EBUDGET) if it
+        had to be queued for memory (it still is: close it or wait for it).
+        queue=True: (id, admitted) -- admitted False when it was queued."""
         arr = _spec_array(specs)
         gid = ctypes.c_uint64()
-        _check(lib().gen_server_open(self.handle, seed, env_base, len(arr), arr,
-                                     ctypes.byref(common) if common else None, 1 if actor_seed is not None else 0,
-                                     actor_seed or 0, ctypes.byref(gid)))
-        return gid.value
+        rc = lib().gen_server_open(self.handle, seed, env_base, len(arr), arr,
+                                   ctypes.byref(common) if common else None, 1 if actor_seed is not None else 0,
+                                   actor_seed or 0, ctypes.byref(gid))
+        if queue and rc == GEN_EBUDGET:
+            return gid.value, False
+        if rc == GEN_EBUDGET:
+            err = GenError(rc, gen_last_error())
+            err.group = gid.value
+            raise err
+        _check(rc)
+        return (gid.value, True) if queue else gid.value
+
+    def wait_admitted(self, group: int, timeout_us: int = -1) -> int:
+        rc = lib().gen_server_wait_admitted(self.handle, group, timeout_us)
+        if rc not in (GEN_OK, GEN_EBUSY):
+            _check(rc)
+        return rc
 
     def buffers(self, group: int) -> dict:
         b = gen_group_buffers()

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -73,6 +74,67 @@ class Arena {
     uint64_t size_ = 0, used_ = 0;
 };
 
+// Latency histogram of fixed size: values in nanoseconds, exact below 64,
+// then 32 buckets per power of two (a bucket spans 1/32 of its lower bound,
+// so a quantile read at the bucket middle is within 1.6% of the sample).
+class LatHist {
+  public:
+    static constexpr int kSub = 32, kTop = 46;         // up to 2^46 ns (about 19 hours)
+    static constexpr int kBuckets = 64 + (kTop - 6) * kSub;
+    void clear()
+    {
+        std::fill(n_, n_ + kBuckets, 0ull);
+        count_ = 0;
+        sum_ns_ = 0.0;
+        max_ns_ = 0;
+    }
+    void add(int64_t ns)
+    {
+        const uint64_t v = ns < 0 ? 0 : (uint64_t)ns;
+        n_[index(v)] += 1;
+        count_ += 1;
+        sum_ns_ += (double)v;
+        max_ns_ = std::max(max_ns_, v);
+    }
+    uint64_t count() const { return count_; }
+    double mean_us() const { return count_ ? sum_ns_ / (double)count_ / 1e3 : 0.0; }
+    double max_us() const { return (double)max_ns_ / 1e3; }
+    // q-quantile (0 < q <= 1): the middle of the bucket holding the
+    // ceil(q * count)-th smallest sample, in microseconds
+    double quantile_us(double q) const
+    {
+        if (count_ == 0) return 0.0;
+        uint64_t rank = (uint64_t)std::ceil(q * (double)count_);
+        if (rank < 1) rank = 1;
+        uint64_t acc = 0;
+        for (int i = 0; i < kBuckets; ++i) {
+            acc += n_[i];
+            if (acc >= rank) return mid(i) / 1e3;
+        }
+        return max_us();
+    }
+
+  private:
+    static int index(uint64_t v)
+    {
+        if (v < 64) return (int)v;
+        int e = 63 - __builtin_clzll(v);                // 2^e <= v < 2^(e+1), e >= 6
+        if (e >= kTop) return kBuckets - 1;
+        return 64 + (e - 6) * kSub + (int)((v >> (e - 5)) & (kSub - 1));
+    }
+    static double mid(int i)
+    {
+        if (i < 64) return (double)i;
+        const int e = 6 + (i - 64) / kSub, m = (i - 64) % kSub;
+        const double lo = std::ldexp((double)(kSub + m), e - 5), width = std::ldexp(1.0, e - 5);
+        return lo + width / 2.0;
+    }
+    uint64_t n_[kBuckets] = {};
+    uint64_t count_ = 0;
+    double sum_ns_ = 0.0;
+    uint64_t max_ns_ = 0;
+};
+
 struct Group {
     uint64_t id = 0;
     gen_pool *pool = nullptr;
@@ -81,8 +143,10 @@ struct Group {
     uint64_t actor_seed = 0;
     uint64_t off_state = 0, off_obs = 0, off_act = 0, off_rew = 0, off_done = 0;
     uint64_t sz_state = 0, sz_obs = 0, sz_act = 0, sz_done = 0;
-    bool busy = false;          // a request of this group is in a launch
+    enum Phase { PENDING, ADMITTING, OPEN } phase = PENDING;   // waiting for memory, maps being made, steppable
+    bool busy = false;          // a request of this group is in a launch, or it is not OPEN yet
     bool closing = false;
+    bool failed = false;        // its admission failed (map generation); its tickets fail
     int waiters = 0;            // clients blocked on cv (close waits for them to leave)
     std::condition_variable cv; // completion of this group's tickets
     std::atomic<uint64_t> completed{0};   // requests finished (lock-free progress check)
@@ -127,11 +191,14 @@ struct gen_server {
     std::thread sched;
     std::atomic<bool> stop{false};
     std::atomic<int64_t> n_queued{0};                  // requests in `queue` (lock-free hint)
-    std::atomic<uint64_t> n_submitted{0};              // submits so far (lock-free hint)
+    std::atomic<uint64_t> n_submitted{0};              // submits and admissions so far (lock-free hint:
+                                                       // either can make a waiting request launchable)
     std::string error;                                 // sticky scheduler error
     // stats
-    uint64_t st_requests = 0, st_frames = 0, st_launches = 0, st_refused = 0, st_launch_envs = 0;
-    std::vector<float> lat_us;
+    std::deque<uint64_t> pending;                      // groups waiting for memory, in order of arrival
+    uint64_t capacity = 0;                             // arena bytes left for groups (after the request tables)
+    uint64_t st_requests = 0, st_frames = 0, st_launches = 0, st_queued = 0, st_launch_envs = 0;
+    LatHist lat;
 };
 
 namespace {
@@ -145,7 +212,7 @@ void complete_slot(gen_server &s, Slot &sl, int status)
         auto it = s.tickets.find(tk);
         if (it != s.tickets.end()) {
             it->second.status = status;
-            if (status == 0) s.lat_us.push_back((float)((t - it->second.t_submit) / 1000.0));
+            if (status == 0) s.lat.add(t - it->second.t_submit);
         }
         auto g = s.groups.find(gid);
         if (g != s.groups.end()) {
@@ -186,6 +253,100 @@ void fill_req(const gen_server &s, const Group &g, uint32_t wg_begin, gen::Serve
     (void)s;
 }
 
+// The five buffers of a group carved out of the arena (lock held); false
+// (nothing kept) if they do not fit now.
+bool carve(gen_server &s, Group &g)
+{
+    uint64_t o[5];
+    const uint64_t sz[5] = {g.sz_state, g.sz_obs, g.sz_act, g.sz_act, g.sz_done};
+    int k = 0;
+    for (; k < 5; ++k)
+        if (!s.alloc.alloc(sz[k], &o[k])) break;
+    if (k < 5) {
+        for (int j = 0; j < k; ++j) s.alloc.release(o[j], sz[j]);
+        return false;
+    }
+    g.off_state = o[0];
+    g.off_obs = o[1];
+    g.off_act = o[2];
+    g.off_rew = o[3];
+    g.off_done = o[4];
+    return true;
+}
+
+void uncarve(gen_server &s, const Group &g)
+{
+    const uint64_t sz[5] = {g.sz_state, g.sz_obs, g.sz_act, g.sz_act, g.sz_done};
+    const uint64_t o[5] = {g.off_state, g.off_obs, g.off_act, g.off_rew, g.off_done};
+    for (int j = 0; j < 5; ++j) s.alloc.release(o[j], sz[j]);
+}
+
+uint64_t group_bytes(const Group &g)
+{
+    auto a = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    return a(g.sz_state) + a(g.sz_obs) + 2 * a(g.sz_act) + a(g.sz_done);
+}
+
+// Generate a carved group's first maps on a stream of its own (blocking;
+// called without the lock).
+int make_maps(gen_server &s, Group &g)
+{
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    int rc = GEN_OK;
+    if (e == hipSuccess) {
+        rc = gen_pool_reset(g.pool, s.arena + g.off_state, g.sz_state, s.arena + g.off_obs,
+                            g.actor ? reinterpret_cast<int32_t *>(s.arena + g.off_act) : nullptr, g.actor_seed, st);
+        if (rc == GEN_OK) e = hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    if (e != hipSuccess) return gen::set_error(GEN_EHIP, hipGetErrorString(e));
+    return rc;
+}
+
+// Groups waiting for memory are admitted in order of arrival as long as
+// the first of them fits (a large group is not overtaken by smaller ones).
+// Called without the lock, after memory was released.
+void admit_pending(gen_server &s)
+{
+    std::vector<Group *> todo;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        while (!s.pending.empty()) {
+            auto it = s.groups.find(s.pending.front());
+            if (it == s.groups.end() || it->second->phase != Group::PENDING) {
+                s.pending.pop_front();
+                continue;
+            }
+            Group &g = *it->second;
+            if (!carve(s, g)) break;
+            g.phase = Group::ADMITTING;
+            s.pending.pop_front();
+            todo.push_back(&g);              // stays in the map: close waits while busy
+        }
+    }
+    for (Group *g : todo) {
+        const int rc = make_maps(s, *g);
+        std::lock_guard<std::mutex> lk(s.mu);
+        g->phase = Group::OPEN;
+        g->busy = false;
+        if (rc == GEN_OK) {
+            s.open_envs += g->n_envs;
+        } else {
+            g->failed = true;
+            uncarve(s, *g);
+            for (auto &[tk, t] : s.tickets)
+                if (t.group == g->id && t.status == 1) t.status = GEN_EHIP;
+        }
+        g->cv.notify_all();
+    }
+    if (!todo.empty()) {
+        // requests already queued for these groups can launch now
+        s.n_submitted.fetch_add(1, std::memory_order_release);
+        s.cv_sched.notify_one();
+    }
+}
+
 void scheduler(gen_server *sp)
 {
     gen_server &s = *sp;
@@ -212,11 +373,22 @@ void scheduler(gen_server *sp)
         }
         const bool queued = s.n_queued.load(std::memory_order_acquire) > 0;
         const uint64_t submits = s.n_submitted.load(std::memory_order_acquire);
-        const bool try_launch = n_busy < (int)ns && queued && (submits != last_submits || now_ns() >= retry_at);
+        const bool stopping = s.stop.load();
+        const bool try_launch =
+            n_busy < (int)ns && queued && (submits != last_submits || now_ns() >= retry_at || stopping);
         if (!any_done && !try_launch) {
-            if (s.stop.load() && n_busy == 0) {
+            if (stopping && n_busy == 0) {
                 // shutting down: leave once nothing more can be launched
                 std::lock_guard<std::mutex> g(s.mu);
+                for (auto it = s.queue.begin(); it != s.queue.end();) {
+                    auto t = s.tickets.find(*it);
+                    if (t == s.tickets.end() || t->second.status != 1) {
+                        it = s.queue.erase(it);
+                        s.n_queued.fetch_sub(1, std::memory_order_release);
+                    } else {
+                        ++it;
+                    }
+                }
                 if (s.queue.empty() || !s.error.empty()) break;
             }
             if (n_busy > 0 || queued) {
@@ -266,7 +438,7 @@ void scheduler(gen_server *sp)
             const int64_t idle = s.open_envs - inflight - ready;
             const int64_t want = s.min_batch_envs > 0 ? s.min_batch_envs : std::max<int64_t>(1, s.open_envs / 4);
             const int64_t deadline = oldest == INT64_MAX ? INT64_MAX : oldest + s.max_wait_us * 1000;
-            launch_now = ready > 0 && (idle <= 0 || ready >= want || now_ns() >= deadline);
+            launch_now = ready > 0 && (idle <= 0 || ready >= want || now_ns() >= deadline || stopping);
             if (!launch_now && ready > 0) retry_at = deadline;
         }
         uint32_t n_req = 0;
@@ -351,6 +523,7 @@ int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_stre
             hipHostMalloc(reinterpret_cast<void **>(&sl.h_table), table_bytes, hipHostMallocDefault) != hipSuccess)
             return sfail(GEN_EHIP, "stream, event or pinned table allocation failed");
     }
+    s->capacity = arena_bytes - s->alloc.used();
     s->sched = std::thread(scheduler, s.get());
     *out = s.release();
     return GEN_OK;
@@ -361,6 +534,16 @@ int gen_server_destroy(gen_server *s)
     if (s == nullptr) return GEN_OK;
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        // groups still waiting for memory will not be admitted: their
+        // requests fail, so the scheduler can drain the rest and stop
+        for (uint64_t id : s->pending) {
+            auto it = s->groups.find(id);
+            if (it == s->groups.end()) continue;
+            for (auto &[tk, t] : s->tickets)
+                if (t.group == id && t.status == 1) t.status = GEN_ENOTFOUND;
+            it->second->cv.notify_all();
+        }
+        s->pending.clear();
         s->stop = true;
     }
     s->cv_sched.notify_all();
@@ -392,48 +575,68 @@ int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_e
     g->sz_obs = std::max<uint64_t>(pool->obs_bytes, 16);
     g->sz_act = pool->n_actions * 4;
     g->sz_done = (uint64_t)n_envs;
+    g->busy = true;              // not steppable until its maps exist
+    Group *gp = g.get();
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        uint64_t o[5];
-        const uint64_t sz[5] = {g->sz_state, g->sz_obs, g->sz_act, g->sz_act, g->sz_done};
-        int k = 0;
-        for (; k < 5; ++k)
-            if (!s->alloc.alloc(sz[k], &o[k])) break;
-        if (k < 5) {
-            for (int j = 0; j < k; ++j) s->alloc.release(o[j], sz[j]);
-            s->st_refused += 1;
+        if (group_bytes(*gp) > s->capacity) {
             gen_pool_destroy(pool);
-            return sfail(GEN_EBUDGET, "group of " + std::to_string(n_envs) + " envs does not fit in the arena");
+            return sfail(GEN_EINVAL, "group of " + std::to_string(n_envs) + " envs needs " +
+                                         std::to_string(group_bytes(*gp)) + " bytes, more than the arena holds");
         }
-        g->off_state = o[0];
-        g->off_obs = o[1];
-        g->off_act = o[2];
-        g->off_rew = o[3];
-        g->off_done = o[4];
-        g->id = s->next_group++;
-        g->busy = true;          // until its maps exist
+        gp->id = s->next_group++;
+        *group = gp->id;
+        const bool now = s->pending.empty() && carve(*s, *gp);
+        gp->phase = now ? Group::ADMITTING : Group::PENDING;
+        s->groups[gp->id] = std::move(g);
+        if (!now) {
+            // queued: admitted by a later close that frees enough memory
+            s->pending.push_back(gp->id);
+            s->st_queued += 1;
+            return sfail(GEN_EBUDGET, "group " + std::to_string(gp->id) + " of " + std::to_string(n_envs) +
+                                          " envs queued until memory frees up");
+        }
     }
-    // generate the maps on this thread's own stream, blocking
-    hipStream_t st = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e == hipSuccess) {
-        rc = gen_pool_reset(pool, s->arena + g->off_state, g->sz_state, s->arena + g->off_obs,
-                            actor ? reinterpret_cast<int32_t *>(s->arena + g->off_act) : nullptr, actor_seed, st);
-        if (rc == GEN_OK) e = hipStreamSynchronize(st);
-        (void)hipStreamDestroy(st);
-    }
+    rc = make_maps(*s, *gp);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (e != hipSuccess || rc != GEN_OK) {
-        const uint64_t sz[5] = {g->sz_state, g->sz_obs, g->sz_act, g->sz_act, g->sz_done};
-        const uint64_t o[5] = {g->off_state, g->off_obs, g->off_act, g->off_rew, g->off_done};
-        for (int j = 0; j < 5; ++j) s->alloc.release(o[j], sz[j]);
-        gen_pool_destroy(pool);
-        return sfail(e != hipSuccess ? GEN_EHIP : rc, e != hipSuccess ? hipGetErrorString(e) : gen_last_error());
+    if (rc != GEN_OK) {
+        const std::string why = gen_last_error();
+        uncarve(*s, *gp);
+        gen_pool_destroy(gp->pool);
+        s->groups.erase(gp->id);        // its id was never returned with GEN_OK, so no one holds tickets
+        return sfail(rc, why);
     }
-    g->busy = false;
-    *group = g->id;
-    s->open_envs += g->n_envs;
-    s->groups[g->id] = std::move(g);
+    gp->phase = Group::OPEN;
+    gp->busy = false;
+    s->open_envs += gp->n_envs;
+    return GEN_OK;
+}
+
+int gen_server_wait_admitted(gen_server *s, uint64_t group, int64_t timeout_us)
+{
+    if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->groups.find(group);
+    if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
+    Group &g = *it->second;
+    const auto deadline = Clock::now() + std::chrono::microseconds(timeout_us < 0 ? 0 : timeout_us);
+    g.waiters += 1;
+    bool timed_out = false;
+    while (g.phase != Group::OPEN && !g.closing) {
+        if (timeout_us < 0) {
+            g.cv.wait(lk);
+        } else if (g.cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            timed_out = g.phase != Group::OPEN && !g.closing;
+            break;
+        }
+    }
+    g.waiters -= 1;
+    if (g.closing) {
+        g.cv.notify_all();
+        return sfail(GEN_ENOTFOUND, "group closed");
+    }
+    if (timed_out) return GEN_EBUSY;
+    if (g.failed) return sfail(GEN_EHIP, "admission of the group failed");
     return GEN_OK;
 }
 
@@ -444,6 +647,8 @@ int gen_server_buffers(gen_server *s, uint64_t group, gen_group_buffers *out)
     auto it = s->groups.find(group);
     if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
     const Group &g = *it->second;
+    if (g.failed) return sfail(GEN_EHIP, "admission of the group failed");
+    if (g.phase != Group::OPEN) return sfail(GEN_EBUSY, "group not admitted yet");
     out->state_off = g.off_state;
     out->obs_off = g.off_obs;
     out->actions_off = g.off_act;
@@ -465,6 +670,7 @@ int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
         if (!s->error.empty()) return sfail(GEN_EHIP, s->error);
         auto it = s->groups.find(group);
         if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
+        if (it->second->failed) return sfail(GEN_EHIP, "admission of the group failed");
         const uint64_t tk = s->next_ticket++;
         s->tickets[tk] = Ticket{group, now_ns(), 1};
         s->queue.push_back(tk);
@@ -510,24 +716,34 @@ int gen_server_wait(gen_server *s, uint64_t ticket, int64_t timeout_us)
 int gen_server_close(gen_server *s, uint64_t group)
 {
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->groups.find(group);
-    if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
-    Group &g = *it->second;
-    g.closing = true;
-    for (auto &[tk, t] : s->tickets)
-        if (t.group == group && t.status == 1) {
-            const bool queued = std::find(s->queue.begin(), s->queue.end(), tk) != s->queue.end();
-            if (queued) t.status = GEN_ENOTFOUND;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->groups.find(group);
+        if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
+        Group &g = *it->second;
+        g.closing = true;
+        for (auto &[tk, t] : s->tickets)
+            if (t.group == group && t.status == 1) {
+                const bool queued = std::find(s->queue.begin(), s->queue.end(), tk) != s->queue.end();
+                if (queued) t.status = GEN_ENOTFOUND;
+            }
+        g.cv.notify_all();
+        if (g.phase == Group::PENDING) {
+            // never admitted: it holds no memory
+            s->pending.erase(std::find(s->pending.begin(), s->pending.end(), group));
+            while (g.waiters > 0) g.cv.wait(lk);
+        } else {
+            // in a launch or being admitted: wait for that to finish
+            while (g.busy || g.waiters > 0) g.cv.wait(lk);
+            if (!g.failed) {
+                uncarve(*s, g);
+                s->open_envs -= g.n_envs;
+            }
         }
-    g.cv.notify_all();
-    while (g.busy || g.waiters > 0) g.cv.wait(lk);
-    const uint64_t sz[5] = {g.sz_state, g.sz_obs, g.sz_act, g.sz_act, g.sz_done};
-    const uint64_t o[5] = {g.off_state, g.off_obs, g.off_act, g.off_rew, g.off_done};
-    for (int j = 0; j < 5; ++j) s->alloc.release(o[j], sz[j]);
-    gen_pool_destroy(g.pool);
-    s->open_envs -= g.n_envs;
-    s->groups.erase(it);
+        gen_pool_destroy(g.pool);
+        s->groups.erase(it);
+    }
+    admit_pending(*s);
     return GEN_OK;
 }
 
@@ -552,25 +768,20 @@ int gen_server_report(gen_server *s, gen_server_stats *out, int32_t reset)
     out->requests = s->st_requests;
     out->frames = s->st_frames;
     out->launches = s->st_launches;
-    out->groups_open = s->groups.size();
-    out->groups_refused = s->st_refused;
+    for (const auto &[id, g] : s->groups) out->groups_open += (g->phase == Group::OPEN && !g->failed) ? 1u : 0u;
+    out->groups_queued = s->st_queued;
+    out->groups_pending = s->pending.size();
     out->arena_bytes = s->arena_bytes;
     out->bytes_in_use = s->alloc.used();
     out->envs_per_launch = s->st_launches ? (double)s->st_launch_envs / (double)s->st_launches : 0.0;
-    if (!s->lat_us.empty()) {
-        std::vector<float> v = s->lat_us;
-        const size_t i50 = v.size() / 2, i99 = std::min(v.size() - 1, (size_t)(v.size() * 0.99));
-        std::nth_element(v.begin(), v.begin() + i50, v.end());
-        out->lat_p50_us = v[i50];
-        std::nth_element(v.begin(), v.begin() + i99, v.end());
-        out->lat_p99_us = v[i99];
-        double sum = 0;
-        for (float x : v) sum += x;
-        out->lat_mean_us = sum / (double)v.size();
-    }
+    out->lat_samples = s->lat.count();
+    out->lat_p50_us = s->lat.quantile_us(0.50);
+    out->lat_p99_us = s->lat.quantile_us(0.99);
+    out->lat_mean_us = s->lat.mean_us();
+    out->lat_max_us = s->lat.max_us();
     if (reset) {
-        s->st_requests = s->st_frames = s->st_launches = s->st_launch_envs = s->st_refused = 0;
-        s->lat_us.clear();
+        s->st_requests = s->st_frames = s->st_launches = s->st_launch_envs = s->st_queued = 0;
+        s->lat.clear();
     }
     return GEN_OK;
 }
@@ -626,8 +837,9 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
             x.spec_begin = spec_begin[(size_t)g];
             x.n_envs = h_group_envs[g];
             x.env_base = (uint64_t)x.spec_begin;
-            const int rc = gen_server_open(s, seed, x.env_base, x.n_envs, h_specs + x.spec_begin, common, 1,
-                                           actor_seed, &x.id);
+            int rc = gen_server_open(s, seed, x.env_base, x.n_envs, h_specs + x.spec_begin, common, 1,
+                                     actor_seed, &x.id);
+            if (rc == GEN_EBUDGET) rc = gen_server_wait_admitted(s, x.id, kDriveWaitUs);   // queued for memory
             if (rc != GEN_OK) { failure = rc; break; }
             cg[(size_t)c].push_back(x);
         }
@@ -680,8 +892,9 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
                 }
                 if (gen_server_close(s, grp.id) != GEN_OK) { failure = GEN_EHIP; break; }
                 grp.env_base = reopen_base.fetch_add((uint64_t)grp.n_envs);
-                const int rc = gen_server_open(s, seed, grp.env_base, grp.n_envs, h_specs + grp.spec_begin, common,
-                                               1, actor_seed, &grp.id);
+                int rc = gen_server_open(s, seed, grp.env_base, grp.n_envs, h_specs + grp.spec_begin, common,
+                                         1, actor_seed, &grp.id);
+                if (rc == GEN_EBUDGET) rc = gen_server_wait_admitted(s, grp.id, kDriveWaitUs);
                 if (rc != GEN_OK) { failure = rc; break; }
                 grp.g = group_of(s, grp.id);
                 grp.steps = 0;

@@ -104,22 +104,56 @@ def test_server_mix_vs_alone(gen):
             at_act += P
 
 
-def test_server_budget_admission(gen):
-    specs = group_specs(200, 5, 20, 24)
-    srv = gen.Server(24 << 20, n_launch_streams=1)
-    opened = []
-    with pytest.raises(gen.GenError) as ei:
-        for i in range(100):
-            opened.append(srv.open(specs, seed=1, env_base=200 * i, common=common(gen), actor_seed=2))
-    assert ei.value.code == gen.GEN_EBUDGET
-    assert 1 <= len(opened) < 100
+def test_server_budget_admission_queue(gen):
+    """Admission by an HBM budget of 1 GiB: opens that do not fit are queued
+    and admitted in order of arrival as closes free memory; a request
+    submitted to a queued group runs once the group is admitted, with the
+    results of a group that fitted at once."""
+    specs = group_specs(16384, 5, 20, 24)
+    srv = gen.Server(1 << 30, n_launch_streams=1)
+    tables = srv.report()["bytes_in_use"]      # the server's own request tables
+    opened = [srv.open(specs, seed=1, env_base=16384 * i, common=common(gen), actor_seed=2, queue=True)
+              for i in range(6)]
+    k = sum(adm for _, adm in opened)
+    assert 1 <= k < 6 and all(adm for _, adm in opened[:k]) and not any(adm for _, adm in opened[k:])
     rep = srv.report()
-    assert rep["groups_refused"] == 1 and rep["bytes_in_use"] <= rep["arena_bytes"]
-    srv.close(opened[0])                   # memory frees up -> the next open is admitted
-    g = srv.open(specs, seed=1, env_base=99999, common=common(gen), actor_seed=2)
-    assert srv.wait(srv.submit(g), WAIT_US) == gen.GEN_OK
-    with pytest.raises(gen.GenError):
-        srv.submit(opened[0])              # closed group
+    assert rep["groups_queued"] == 6 - k and rep["groups_pending"] == 6 - k and rep["groups_open"] == k
+    assert rep["bytes_in_use"] <= rep["arena_bytes"]
+    first_q = opened[k][0]
+    with pytest.raises(gen.GenError) as ei:
+        srv.buffers(first_q)                   # not admitted yet
+    assert ei.value.code == gen.GEN_EBUSY
+    tk = srv.submit(first_q)                   # queued behind the admission
+    assert srv.wait(tk, 200_000) == gen.GEN_EBUSY
+    assert srv.wait_admitted(first_q, 0) == gen.GEN_EBUSY
+    last_q = opened[-1][0]
+    srv.close(last_q)                          # a queued group leaves the queue
+    with pytest.raises(gen.GenError) as ei:
+        srv.wait_admitted(last_q, 0)
+    assert ei.value.code == gen.GEN_ENOTFOUND
+    srv.close(opened[0][0])                    # memory frees up -> the first queued group is admitted
+    assert srv.wait_admitted(first_q, WAIT_US) == gen.GEN_OK
+    assert srv.wait(tk, WAIT_US) == gen.GEN_OK
+    rep = srv.report()
+    assert rep["groups_pending"] == max(0, 6 - k - 2)
+    # the queued group's step equals that of a group opened with room to spare
+    ref = gen.Server(1 << 30, n_launch_streams=1)
+    g_ref = ref.open(specs, seed=1, env_base=16384 * k, common=common(gen), actor_seed=2)
+    assert ref.wait(ref.submit(g_ref), WAIT_US) == gen.GEN_OK
+    got, want = snapshot(srv, first_q, specs), snapshot(ref, g_ref, specs)
+    for x, y in zip(got[0][:64], want[0][:64]):
+        for key in KEYS:
+            assert np.array_equal(x[key], y[key])
+    for x, y in zip(got[1:], want[1:]):
+        assert np.array_equal(x, y)
+    ref.close_server()
+    with pytest.raises(gen.GenError) as ei:    # larger than the whole arena: refused, not queued
+        srv.open(group_specs(200000, 6, 24, 24), seed=1, common=common(gen), actor_seed=2)
+    assert ei.value.code == gen.GEN_EINVAL
+    for g, _ in opened[1:-1]:
+        srv.close(g)
+    rep = srv.report()
+    assert rep["groups_open"] == 0 and rep["groups_pending"] == 0 and rep["bytes_in_use"] == tables
     srv.close_server()
 
 
