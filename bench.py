@@ -93,6 +93,33 @@ def traffic_for(wl_name: str, n_launch_frames: int):
     return rec.get("bytes_per_launch")
 
 
+LDS_BYTES_PER_CLK_CU = 128          # 32 banks x 4 bytes per clock per CU
+N_CU, CLK_GHZ = 256, 2.4
+LDS_PEAK_GBS = LDS_BYTES_PER_CLK_CU * N_CU * CLK_GHZ     # 78,643 GB/s
+
+
+def lds_for(wl_name: str, avg_s: float):
+    """LDS bandwidth of the step kernel: the LDS's busy cycles on indexed
+    operations without the bank-conflict stall cycles (SQ_LDS_IDX_ACTIVE -
+    SQ_LDS_BANK_CONFLICT, summed over the CUs, from the committed counter
+    summary) x 128 bytes per cycle, per launch, over the kernel's live
+    average duration; against 128 B/clk x 256 CUs x 2.4 GHz.  None if the
+    counters were taken on another kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(wl_name)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_hash() or "lds_active_cycles" not in rec:
+        return None
+    busy = rec["lds_active_cycles"] - rec["lds_conflict_cycles"]
+    by = busy * LDS_BYTES_PER_CLK_CU
+    ach = by / avg_s / 1e9
+    return {"achieved": ach, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": ach / LDS_PEAK_GBS,
+            "bytes_per_launch": by, "bank_conflict_share": rec["lds_conflict_cycles"] / max(1.0, rec["lds_active_cycles"]),
+            "source": rec.get("summary")}
+
+
 def copy_ceiling_gbs(gen, torch, n_bytes: int = 1 << 30, reps: int = 20) -> float:
     """Bandwidth of the library's streaming copy kernel (16-byte nontemporal
     loads and stores; read + write bytes / time): the practical ceiling of
@@ -287,7 +314,7 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
                                  "ms_per_step": bucket_s * 1e3},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": bpf,
-                         "traffic": traffic_for(wl.name, wl.n_envs)}}
+                         "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, step_s)}}
 
 
 def run_served_c2(gen, torch, duration_s: float) -> dict:
@@ -368,7 +395,7 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int) -> dict:
             "step_kernel_ms_mean": avg * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": by["step"],
-                         "traffic": traffic_for(wl.name, wl.n_envs)}}
+                         "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, avg)}}
 
 
 def host_cores() -> int:
@@ -516,7 +543,7 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_env<STEP, actor fused> (gen_step_sample)",
                      "algorithmic_bytes_per_frame": by["step"],
-                     "frames_per_launch": E},
+                     "frames_per_launch": E, "lds": lds_for(wl.name, avg_step_s)},
     }
     legs = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
     unknown = legs - set(EXTRAS)

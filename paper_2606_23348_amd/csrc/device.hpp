@@ -56,7 +56,16 @@ struct GenParamsDev {
 
 // ---------------------------------------------------------------- wave ops
 // Make LDS writes of one lane visible to the other lanes of the same wave and
-// keep the compiler from moving LDS accesses across this point.
+// keep the compiler from moving LDS accesses across this point.  What it
+// relies on: (1) the release fence makes the wave wait for its own
+// outstanding LDS operations (s_waitcnt lgkmcnt(0)) before anything after
+// it issues, and the acquire fence keeps later LDS reads after that point;
+// (2) the wave barrier is a compiler-only barrier for one wave (its lanes
+// run in lockstep, so no hardware barrier is needed); (3) LDS accesses of
+// one wave take effect in the order the wave issues them.  Code between
+// two wave_sync calls may read a location another lane wrote only if the
+// write came before the first call.  Data passed through registers
+// (readlane, ds_bpermute, DPP) needs no wave_sync.
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
