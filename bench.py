@@ -260,26 +260,40 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
                  for gr in (0, 8 * n_cus)]
         best, table = tuner.tune(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, steps=8, cache_path=None,
                                  cands=cands, progress=log)
-    pool = gen.Pool(specs, common, seed=wl.seed)
-    s = torch.cuda.Stream()
-    K = 10
-    with torch.cuda.stream(s):
-        pool.set_tuning(**best, stream=s)
-        pool.reset(actor_seed=wl.actor_seed, stream=s)
-        pool.capture(K, wl.actor_seed, s)
-        pool.replay(s)
-        s.synchronize()
-        reps = max(1, steps // K)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
+    buckets, bucket_report = [], {}
+    if tune_it:
+        buckets, bucket_report = tuner.tune_buckets(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, base=best,
+                                                    steps=8, cache_path=None, progress=log)
+
+    def timed(table) -> float:
+        """Seconds per step of graph replays (K steps per graph) with the
+        pool-wide packing `best` and the per-bucket table."""
+        pool = gen.Pool(specs, common, seed=wl.seed)
+        s = torch.cuda.Stream()
+        K = 10
+        with torch.cuda.stream(s):
+            pool.set_tuning(**best, stream=s)
+            pool.set_buckets(table, stream=s)
+            pool.reset(actor_seed=wl.actor_seed, stream=s)
+            pool.capture(K, wl.actor_seed, s)
             pool.replay(s)
-        e1.record(s)
-        s.synchronize()
-    step_s = e0.elapsed_time(e1) / 1e3 / (reps * K)
+            s.synchronize()
+            reps = max(1, steps // K)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                pool.replay(s)
+            e1.record(s)
+            s.synchronize()
+        del pool
+        torch.cuda.empty_cache()
+        return e0.elapsed_time(e1) / 1e3 / (reps * K)
+
+    single_s = timed([])
+    table_s = timed(buckets) if buckets else single_s
+    step_s = min(single_s, table_s)
     bpf = pool_bytes_per_frame(specs)
     achieved = bpf * wl.n_envs / step_s / 1e9
-    del pool
     # baseline: each (H, W, mode, P) bucket as its own plain batch, one launch each per step
     keys = np.stack([specs["H"], specs["W"], specs["mode"], specs["P"]], 1)
     uniq, inv = np.unique(keys, axis=0, return_inverse=True)
@@ -308,8 +322,12 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
     del batches
     torch.cuda.empty_cache()
     return {"workload": wl.name, "n_envs": wl.n_envs, "frames_per_s": wl.n_envs / step_s,
-            "ms_per_step": step_s * 1e3, "graph_steps": K, "tuning": best,
+            "ms_per_step": step_s * 1e3, "graph_steps": 10, "tuning": best,
             "tuning_candidates": len(table),
+            "per_bucket_tuning": {"table": buckets, "ms_per_step_best_single_packing": single_s * 1e3,
+                                  "ms_per_step_per_bucket": table_s * 1e3,
+                                  "gain_over_single": single_s / table_s - 1.0, "used": table_s < single_s,
+                                  "candidates_us": bucket_report},
             "per_bucket_plain": {"buckets": int(len(uniq)), "frames_per_s": wl.n_envs / bucket_s,
                                  "ms_per_step": bucket_s * 1e3},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -368,11 +386,13 @@ def run_served_mix(gen, torch, duration_s: float) -> dict:
             "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
 
 
-def run_plain_leg(gen, torch, wl, steps: int, warmup: int) -> dict:
+def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) -> dict:
     """Another plain workload in the headline's form: `warmup` untimed
     fused launches, then `steps` timed back to back between one pair of HIP
-    events on the launch stream."""
-    b = gen.Batch(wl.n_envs, wl.H, wl.W, wl.mode, gen.make_params(wl.mode, wl.P, **wl.params()), seed=wl.seed)
+    events on the launch stream.  obs_layout 1: observation planes padded to
+    32 bytes (the algorithmic bytes stay those of the dense planes)."""
+    b = gen.Batch(wl.n_envs, wl.H, wl.W, wl.mode,
+                  gen.make_params(wl.mode, wl.P, obs_layout=obs_layout, **wl.params()), seed=wl.seed)
     stream = torch.cuda.current_stream()
     b.sample(wl.actor_seed, 0)
     for t in range(warmup):
@@ -389,13 +409,15 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int) -> dict:
     avg = r0.elapsed_time(r1) / 1e3 / steps
     by = step_bytes(wl)
     achieved = by["step"] * wl.n_envs / avg / 1e9
+    key = wl.name + ("-padded" if obs_layout else "")       # counter records are per layout
     del b
     torch.cuda.empty_cache()
-    return {"workload": wl.name, "steps": steps, "warmup": warmup, "frames_per_s": wl.n_envs * steps / elapsed,
+    return {"workload": wl.name, "obs_layout": "planes padded to 32 bytes" if obs_layout else "dense [E,P,8,H,W]",
+            "steps": steps, "warmup": warmup, "frames_per_s": wl.n_envs * steps / elapsed,
             "step_kernel_ms_mean": avg * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": by["step"],
-                         "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, avg)}}
+                         "traffic": traffic_for(key, wl.n_envs), "lds": lds_for(key, avg)}}
 
 
 def host_cores() -> int:
@@ -563,7 +585,8 @@ def main() -> int:
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(gen, torch)
     if "c3" in legs:
         log("FFA-8 leg")
-        out["c3"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W)
+        out["c3"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W, obs_layout=1)
+        out["c3_dense"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W, obs_layout=0)
     if "rollout" in legs:
         log("rollout leg")
         out["rollout"] = run_rollout(gen, torch)

@@ -89,7 +89,14 @@ typedef struct gen_params {
     int32_t max_general_dist;   /* generator 1: cap on the BFS distance between generals
                                    (the spawn-distance curriculum, Section V-C); 0 = none */
     int32_t castle_radius;      /* generator 1: BFS radius of the guaranteed castle (6) */
-    int32_t reserved[4];        /* must be zero */
+    int32_t obs_layout;         /* observation layout of the plain-batch calls (gen_step,
+                                   gen_step_sample, gen_observe, gen_reset): 0 = dense
+                                   uint8 [E][P][8][H][W]; 1 = each plane H*W bytes then
+                                   zero bytes up to a multiple of 32, uint8 [E][P][8][PS]
+                                   with PS = (H*W + 31) & ~31 (the same as 0 when H*W is
+                                   a multiple of 32).  1 lets every env's planes be written
+                                   with aligned streaming stores.  Pools always use 1. */
+    int32_t reserved[3];        /* must be zero */
 } gen_params;
 
 /* Descriptor of one batch of identical envs living in one device buffer.
@@ -277,7 +284,12 @@ int gen_set_state(const gen_state *st, const gen_host_state *h, void *stream);
  * Each env keeps its own shape (3..32 per side), mode, player count and
  * generator settings; the state lives in one caller-provided device buffer
  * (layout private to the library), observations, actions and rewards in
- * ragged caller buffers at the offsets gen_pool_offsets reports.  The random
+ * ragged caller buffers at the offsets gen_pool_offsets reports.  An env's
+ * observation block holds its [P][8] planes (channels as in gen_step), each
+ * plane H*W bytes row-major followed by zero bytes up to a multiple of 32
+ * (plane stride PS = (H*W + 31) & ~31, so plane (p, ch) starts at byte
+ * (8p + ch) * PS of the block): every plane starts on a 32-byte sector and
+ * the whole block is written with aligned 4-byte streaming stores.  The random
  * actor of a pool draws with each env's own step counter (0 at reset, +1
  * per step) as its step index, so a captured graph can be replayed any
  * number of times and keeps drawing fresh actions.
@@ -295,7 +307,7 @@ typedef struct gen_pool_info {
     int32_t n_envs;
     int32_t max_cells;          /* largest H*W in the pool */
     uint64_t state_bytes;       /* device state buffer to pass to gen_pool_reset */
-    uint64_t obs_bytes;         /* ragged observation buffer (each env block 16-byte aligned) */
+    uint64_t obs_bytes;         /* ragged observation buffer (each env block P*8*PS bytes, 16-byte aligned) */
     uint64_t n_actions;         /* int32 entries of the ragged actions and rewards buffers (sum of P) */
     uint64_t work_list_off;     /* the work list inside the state buffer: the only bytes */
     uint64_t work_list_bytes;   /* of the state that depend on the packing (gen_pool_tuning) */
@@ -310,6 +322,21 @@ typedef struct gen_pool_tuning {
     int32_t waves_per_group, grid, order, reserved;
 } gen_pool_tuning;
 
+/* Packing of one size bucket of a pool: the envs with n_players players
+ * whose map takes `words` 64-cell words (ceil(H*W / 64)).  Envs of buckets
+ * that share a packing are stepped by one launch; a pool with several
+ * packings takes one launch per distinct packing each step.
+ *   waves_per_group  1, 2 or 4 envs (one wave each) per workgroup;
+ *   waves_per_env    1, or 2: a second wave of the env's workgroup writes
+ *                    the observation planes of players floor(3P/8) .. P-1
+ *                    (then waves_per_group must be 1). */
+typedef struct gen_pool_bucket {
+    int32_t n_players, words;
+    int32_t n_envs;             /* envs of the pool in the bucket (filled by gen_pool_buckets; ignored on set) */
+    int32_t waves_per_group, waves_per_env;
+    int32_t reserved[3];        /* must be zero */
+} gen_pool_bucket;
+
 /* Plan a pool of n_envs envs described by h_specs[n_envs] (host).  `common`
  * supplies the mountain threshold, city armies, auto_reset and pregrow
  * (NULL: defaults); its city counts, spawn distance and n_players are
@@ -323,8 +350,19 @@ int gen_pool_query(const gen_pool *pool, gen_pool_info *out);
 int gen_pool_offsets(const gen_pool *pool, uint64_t *h_obs_off, uint32_t *h_act_off);
 int gen_pool_get_tuning(const gen_pool *pool, gen_pool_tuning *out);
 /* Takes effect at the next launch (uploads the work list if the pool is bound;
- * blocking on `stream`).  Results never depend on the packing. */
+ * blocking on `stream`).  Results never depend on the packing.  The
+ * pool-wide waves_per_group applies to the buckets gen_pool_set_buckets does
+ * not list (and to the reset launch); grid applies to every one-wave-per-env
+ * launch. */
 int gen_pool_set_tuning(gen_pool *pool, const gen_pool_tuning *tuning, void *stream);
+/* The pool's size buckets (in order of n_players, then words) with their
+ * env counts and current packing: *n_out = number of buckets; up to
+ * `capacity` of them are written to out (NULL allowed to query the count). */
+int gen_pool_buckets(const gen_pool *pool, gen_pool_bucket *out, int32_t capacity, int32_t *n_out);
+/* Set the packing of the listed buckets (others keep the pool-wide one);
+ * n = 0 clears the table.  Same effect rules as gen_pool_set_tuning.  A
+ * captured graph keeps the launches it captured: capture again after. */
+int gen_pool_set_buckets(gen_pool *pool, const gen_pool_bucket *table, int32_t n, void *stream);
 /* Bind the state buffer (>= state_bytes, 256-byte aligned), generate every
  * env's first map, write observations (d_obs nullable) and, if d_actions is
  * not NULL, the random actor's actions for step 0. */

@@ -35,7 +35,7 @@ class gen_params(ctypes.Structure):
                 ("min_general_dist", ctypes.c_int32), ("auto_reset", ctypes.c_int32),
                 ("pregrow", ctypes.c_int32), ("generator", ctypes.c_int32),
                 ("max_general_dist", ctypes.c_int32), ("castle_radius", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("obs_layout", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class gen_state(ctypes.Structure):
@@ -66,6 +66,12 @@ class gen_pool_info(ctypes.Structure):
 
 class gen_pool_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("waves_per_group", "grid", "order", "reserved")]
+
+
+class gen_pool_bucket(ctypes.Structure):
+    _fields_ = [("n_players", ctypes.c_int32), ("words", ctypes.c_int32), ("n_envs", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("waves_per_env", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class gen_group_buffers(ctypes.Structure):
@@ -126,6 +132,8 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_pool_offsets.argtypes = [vp, vp, vp]
     L.gen_pool_get_tuning.argtypes = [vp, P(gen_pool_tuning)]
     L.gen_pool_set_tuning.argtypes = [vp, P(gen_pool_tuning), vp]
+    L.gen_pool_buckets.argtypes = [vp, vp, i32, P(i32)]
+    L.gen_pool_set_buckets.argtypes = [vp, vp, i32, vp]
     L.gen_pool_reset.argtypes = [vp, vp, u64, vp, vp, u64, vp]
     L.gen_pool_step.argtypes = [vp, vp, i32, u64, vp, vp, vp, vp]
     L.gen_pool_capture.argtypes = [vp, i32, vp, u64, vp, vp, vp, vp]
@@ -149,7 +157,7 @@ def load_library(path: str) -> ctypes.CDLL:
     for f in ("gen_default_params", "gen_layout", "gen_reset", "gen_step", "gen_step_sample", "gen_sample_actions",
               "gen_observe", "gen_features", "gen_rollout", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
-              "gen_pool_set_tuning", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
+              "gen_pool_set_tuning", "gen_pool_buckets", "gen_pool_set_buckets", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
               "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_get_envs_static", "gen_server_create", "gen_server_destroy", "gen_server_open", "gen_server_wait_admitted",
               "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
               "gen_server_report", "gen_server_set_batching", "gen_server_drive"):
@@ -338,9 +346,12 @@ class Batch:
         lay = gen_layout(n_envs, H, W, mode, params, seed)
         P = lay.n_players
         self.n_envs, self.H, self.W, self.mode, self.P = n_envs, H, W, mode, P
+        self.padded = params is not None and params.obs_layout == 1
+        self.PS = plane_stride(H, W) if self.padded else H * W
         # zero-filled, so alignment padding the library never writes is deterministic
         self.buf = torch.zeros(lay.bytes, dtype=torch.uint8, device=device)
-        self.obs = torch.zeros((n_envs, P, 8, H, W), dtype=torch.uint8, device=device) if with_obs else None
+        obs_shape = (n_envs, P, 8, self.PS) if self.padded else (n_envs, P, 8, H, W)
+        self.obs = torch.zeros(obs_shape, dtype=torch.uint8, device=device) if with_obs else None
         self.actions = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
         self.rewards = torch.zeros((n_envs, P), dtype=torch.int32, device=device)
         self.dones = torch.zeros(n_envs, dtype=torch.uint8, device=device)
@@ -348,6 +359,14 @@ class Batch:
         self.army = torch.zeros((n_envs, P), dtype=torch.int64, device=device) if scoreboard else None
         self.feat = self.fmem = self.tokens = None   # 38-channel features, allocated by features()
         self.st = gen_reset(seed, env_base, n_envs, H, W, mode, params, self.buf, self.obs, stream)
+
+    def obs_dense(self) -> np.ndarray:
+        """The observation on the host as uint8 [E, P, 8, H, W] (without the
+        plane padding of obs_layout 1)."""
+        o = self.obs.cpu().numpy()
+        if self.padded:
+            o = np.ascontiguousarray(o[..., :self.H * self.W])
+        return o.reshape(self.n_envs, self.P, 8, self.H, self.W)
 
     def sample(self, actor_seed: int, step_idx: int, stream=None):
         gen_sample_actions(self.st, actor_seed, step_idx, self.actions, stream)
@@ -482,6 +501,25 @@ class Pool:
         t = gen_pool_tuning(waves_per_group, grid, order, 0)
         _check(lib().gen_pool_set_tuning(self.handle, ctypes.byref(t), _stream(stream)))
 
+    def buckets(self) -> list:
+        """The pool's size buckets: dicts of n_players, words, n_envs and the
+        packing (waves_per_group, waves_per_env)."""
+        n = ctypes.c_int32()
+        _check(lib().gen_pool_buckets(self.handle, None, 0, ctypes.byref(n)))
+        arr = (gen_pool_bucket * max(1, n.value))()
+        _check(lib().gen_pool_buckets(self.handle, arr, n.value, ctypes.byref(n)))
+        return [{k: getattr(arr[i], k) for k in ("n_players", "words", "n_envs", "waves_per_group", "waves_per_env")}
+                for i in range(n.value)]
+
+    def set_buckets(self, table: list, stream=None):
+        """Per-bucket packing: a list of dicts with n_players, words,
+        waves_per_group and waves_per_env ([] clears it)."""
+        arr = (gen_pool_bucket * max(1, len(table)))()
+        for i, t in enumerate(table):
+            arr[i] = gen_pool_bucket(int(t["n_players"]), int(t["words"]), 0, int(t["waves_per_group"]),
+                                     int(t.get("waves_per_env", 1)))
+        _check(lib().gen_pool_set_buckets(self.handle, arr, len(table), _stream(stream)))
+
     def get_env(self, e: int, stream=None) -> dict:
         HW = int(self.specs["H"][e]) * int(self.specs["W"][e])
         h = _host_arrays(1, HW, int(self.specs["P"][e]))
@@ -518,13 +556,25 @@ class Pool:
         return h.hexdigest()
 
     def env_obs(self, e: int):
-        H, W, P = (int(self.specs[k][e]) for k in ("H", "W", "P"))
-        o = int(self.obs_off[e])
-        return self.obs[o:o + P * 8 * H * W].view(P, 8, H, W)
+        """Env e's observation [P, 8, H*W] (a strided view: planes are padded
+        to a multiple of 32 bytes)."""
+        return pool_env_obs(self.obs, int(self.obs_off[e]), *(int(self.specs[k][e]) for k in ("H", "W", "P")))
 
     def env_slice(self, e: int):
         a = int(self.act_off[e])
         return slice(a, a + int(self.specs["P"][e]))
+
+
+def plane_stride(H: int, W: int) -> int:
+    """Bytes between two planes of a pool env's observation block."""
+    return (H * W + 31) & ~31
+
+
+def pool_env_obs(obs, off: int, H: int, W: int, P: int):
+    """The [P, 8, H*W] observation of the pool env whose block starts at byte
+    `off` of a ragged observation buffer (torch tensor or numpy array)."""
+    PS = plane_stride(H, W)
+    return obs[off:off + P * 8 * PS].reshape(P, 8, PS)[:, :, :H * W]
 
 
 # ---------------------------------------------------------------------------- served form

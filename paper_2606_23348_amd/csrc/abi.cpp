@@ -66,7 +66,8 @@ int check_params(const gen_params &p, int P, int HW)
         return fail(GEN_EINVAL, "max_general_dist %d outside [0, %d]", p.max_general_dist, GEN_MAX_CELLS);
     if (p.castle_radius < 0 || p.castle_radius > 64)
         return fail(GEN_EINVAL, "castle_radius %d outside [0, 64]", p.castle_radius);
-    for (int i = 0; i < 4; ++i)
+    if (p.obs_layout != 0 && p.obs_layout != 1) return fail(GEN_EINVAL, "obs_layout must be 0 or 1");
+    for (int i = 0; i < 3; ++i)
         if (p.reserved[i] != 0) return fail(GEN_EINVAL, "gen_params.reserved must be zero");
     (void)P;
     return GEN_OK;
@@ -84,7 +85,7 @@ gen::Geom geom_of(const gen_state &st)
     g.NW = (g.HW + 63) / 64;
     g.magic_w = (uint32_t)(((1u << 20) + (uint32_t)st.W - 1) / (uint32_t)st.W);
     g.magic_hw = (uint32_t)(((uint64_t(1) << 32) + (uint64_t)g.HW - 1) / (uint64_t)g.HW);
-    g.obsv = gen::obs_variant(g.HW, g.P);
+    g.PS = st.params.obs_layout == 1 ? gen::pool_plane_stride(g.HW) : g.HW;
     return g;
 }
 
@@ -123,7 +124,9 @@ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
 {
     if (d_obs == nullptr) return GEN_OK;
-    const uint64_t B = (uint64_t)st.n_players * 8 * st.H * st.W;
+    const uint64_t PS = st.params.obs_layout == 1 ? (uint64_t)gen::pool_plane_stride(st.H * st.W)
+                                                  : (uint64_t)st.H * st.W;
+    const uint64_t B = (uint64_t)st.n_players * 8 * PS;
     const uintptr_t need = (B % 16 == 0) ? 16 : 8;
     if (!aligned(d_obs, need)) return fail(GEN_EINVAL, "d_obs must be %u-byte aligned", (unsigned)need);
     return GEN_OK;
@@ -195,14 +198,61 @@ int gather_to_host(const gen_state &st, const int32_t *h_env_ids, int32_t n_ids,
 
 namespace {
 
+// Size bucket of env i: (players, 64-cell words of its map).
+std::pair<int, int> bucket_of(const gen_pool &pl, size_t i)
+{
+    const gen::PoolDesc &d = pl.desc[i];
+    return {(int)d.P, ((int)d.H * (int)d.W + 63) / 64};
+}
+
+// Packing (waves per group, waves per env) of env i: its bucket's entry of
+// the table, else the pool-wide waves per group and one wave per env.
+std::pair<uint32_t, uint32_t> packing_of(const gen_pool &pl, size_t i)
+{
+    const auto b = bucket_of(pl, i);
+    for (const gen_pool_bucket &t : pl.buckets)
+        if (t.n_players == b.first && t.words == b.second)
+            return {(uint32_t)t.waves_per_group, (uint32_t)t.waves_per_env};
+    return {(uint32_t)pl.tuning.waves_per_group, 1u};
+}
+
+// Work list: envs grouped into segments of one packing (in order of the
+// packing), inside a segment in env order or largest first (tuning.order).
 void pool_make_order(gen_pool &pl)
 {
-    pl.order.resize((size_t)pl.n);
-    for (int32_t i = 0; i < pl.n; ++i) pl.order[(size_t)i] = (uint32_t)i;
-    if (pl.tuning.order == 1) {
-        std::stable_sort(pl.order.begin(), pl.order.end(),
-                         [&](uint32_t a, uint32_t b) { return pl.work[a] > pl.work[b]; });
+    const size_t n = (size_t)pl.n;
+    std::vector<uint32_t> key(n);
+    for (size_t i = 0; i < n; ++i) {
+        const auto pk = packing_of(pl, i);
+        key[i] = pk.first * 4 + pk.second;            // distinct per (waves_per_group, waves_per_env)
     }
+    pl.order.resize(n);
+    for (size_t i = 0; i < n; ++i) pl.order[i] = (uint32_t)i;
+    std::stable_sort(pl.order.begin(), pl.order.end(), [&](uint32_t a, uint32_t b) {
+        if (key[a] != key[b]) return key[a] < key[b];
+        return pl.tuning.order == 1 && pl.work[a] > pl.work[b];
+    });
+    pl.segments.clear();
+    for (size_t s = 0; s < n;) {
+        size_t e = s;
+        while (e < n && key[pl.order[e]] == key[pl.order[s]]) ++e;
+        const auto pk = packing_of(pl, pl.order[s]);
+        pl.segments.push_back({(uint32_t)s, (uint32_t)e, pk.first, pk.second});
+        s = e;
+    }
+}
+
+// One step of every env: one launch per segment of the work list.
+hipError_t pool_step_launches(const gen_pool &pl, gen::PoolArgs a, bool act, hipStream_t s)
+{
+    for (const auto &sg : pl.segments) {
+        a.slot_begin = sg.begin;
+        a.slot_end = sg.end;
+        a.wpg = sg.wpg;
+        const hipError_t e = gen::launch_pool(a, 0 /* step */, act, (uint32_t)pl.tuning.grid, sg.nwv, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 gen::PoolArgs pool_args(const gen_pool &pl)
@@ -212,11 +262,12 @@ gen::PoolArgs pool_args(const gen_pool &pl)
     a.seed = pl.seed;
     a.env_base = pl.env_base;
     a.n_envs = (uint32_t)pl.n;
+    a.slot_begin = 0;
+    a.slot_end = (uint32_t)pl.n;
     a.wpg = (uint32_t)pl.tuning.waves_per_group;
     a.lds_per_wave = pl.lds_per_wave;
     uint8_t *base = static_cast<uint8_t *>(pl.d_state);
     a.desc = reinterpret_cast<const gen::PoolDesc *>(base + pl.off_desc);
-    a.order = reinterpret_cast<const uint32_t *>(base + pl.off_order);
     a.sc = reinterpret_cast<gen::EnvScalars *>(base + pl.off_scalars);
     a.owner = reinterpret_cast<int8_t *>(base + pl.off_owner);
     a.type = base + pl.off_type;
@@ -224,10 +275,14 @@ gen::PoolArgs pool_args(const gen_pool &pl)
     return a;
 }
 
-int pool_upload_order(gen_pool &pl, hipStream_t s)
+// The device work list: the envs' descriptors in slot order (each carries
+// its env index), so a wave reaches its env's geometry with one load.
+int pool_upload_work(gen_pool &pl, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(pl.d_state) + pl.off_order, pl.order.data(),
-                                  pl.order.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    std::vector<gen::PoolDesc> work(pl.order.size());
+    for (size_t i = 0; i < work.size(); ++i) work[i] = pl.desc[pl.order[i]];
+    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(pl.d_state) + pl.off_desc, work.data(),
+                                  work.size() * sizeof(gen::PoolDesc), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? GEN_OK : hip_fail(e, "pool work-list upload");
 }
@@ -599,15 +654,7 @@ int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream
     if (d_dst == nullptr || d_src == nullptr || !aligned(d_dst, 16) || !aligned(d_src, 16) || bytes % 16 != 0)
         return fail(GEN_EINVAL, "gen_stream_copy needs 16-byte aligned buffers and a multiple of 16 bytes");
     if (bytes == 0) return ok();
-    int dev = 0, n_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e, "device query");
-    const uint64_t n16 = bytes / 16;
-    // 8 workgroups of 256 threads per CU: enough loads in flight to cover
-    // HBM latency; the grid strides over larger buffers
-    const uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>((n16 + 255) / 256, (uint64_t)n_cu * 8));
-    e = gen::launch_stream_copy(d_dst, d_src, n16, (uint32_t)want, static_cast<hipStream_t>(stream));
+    hipError_t e = gen::launch_stream_copy(d_dst, d_src, bytes / 16, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "copy launch");
     return ok();
 }
@@ -662,10 +709,10 @@ int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_
         d.cmin = (uint8_t)sp.cities_min;
         d.cmax = (uint8_t)sp.cities_max;
         d.dmin = (uint8_t)sp.min_general_dist;
-        d.obsv = (uint8_t)g.obsv;
-        d.reserved = 0;
+        d.pad8 = 0;
+        d.env = (uint32_t)i;
         cells += (uint64_t)st.stride;
-        obs16 += ((uint64_t)st.n_players * 8 * sp.H * sp.W + 15) / 16;
+        obs16 += ((uint64_t)st.n_players * 8 * (uint64_t)gen::pool_plane_stride(sp.H * sp.W) + 15) / 16;
         acts += (uint64_t)st.n_players;
         pl->work[(size_t)i] = (uint64_t)st.n_players * sp.H * sp.W;
         if (st.stride > max_s) max_s = st.stride;
@@ -679,8 +726,7 @@ int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_
     const uint64_t E = (uint64_t)n_envs;
     pl->off_scalars = 0;
     pl->off_desc = align256(E * sizeof(gen::EnvScalars));
-    pl->off_order = pl->off_desc + align256(E * sizeof(gen::PoolDesc));
-    pl->off_owner = pl->off_order + align256(E * sizeof(uint32_t));
+    pl->off_owner = pl->off_desc + align256(E * sizeof(gen::PoolDesc));
     pl->off_type = pl->off_owner + align256(cells);
     pl->off_army = pl->off_type + align256(cells);
     pl->state_bytes = pl->off_army + align256(cells * 4);
@@ -709,8 +755,8 @@ int gen_pool_query(const gen_pool *pool, gen_pool_info *out)
     out->state_bytes = pool->state_bytes;
     out->obs_bytes = pool->obs_bytes;
     out->n_actions = pool->n_actions;
-    out->work_list_off = pool->off_order;
-    out->work_list_bytes = (uint64_t)pool->n * sizeof(uint32_t);
+    out->work_list_off = pool->off_desc;
+    out->work_list_bytes = (uint64_t)pool->n * sizeof(gen::PoolDesc);
     return ok();
 }
 
@@ -740,12 +786,62 @@ int gen_pool_set_tuning(gen_pool *pool, const gen_pool_tuning *t, void *stream)
         return fail(GEN_EINVAL, "grid must be >= 0, order 0 or 1, reserved 0");
     if ((uint64_t)pool->lds_per_wave * (uint64_t)t->waves_per_group > 65536)
         return fail(GEN_EINVAL, "%d waves per group need more than 64 KiB of LDS", t->waves_per_group);
-    const bool reorder = t->order != pool->tuning.order;
     pool->tuning = *t;
-    if (reorder) {
-        pool_make_order(*pool);
-        if (pool->d_state) return pool_upload_order(*pool, static_cast<hipStream_t>(stream)) == GEN_OK ? ok() : GEN_EHIP;
+    pool_make_order(*pool);
+    if (pool->d_state) return pool_upload_work(*pool, static_cast<hipStream_t>(stream)) == GEN_OK ? ok() : GEN_EHIP;
+    return ok();
+}
+
+int gen_pool_buckets(const gen_pool *pool, gen_pool_bucket *out, int32_t capacity, int32_t *n_out)
+{
+    if (pool == nullptr || n_out == nullptr) return fail(GEN_EINVAL, "pool and n_out are required");
+    if (capacity < 0 || (capacity > 0 && out == nullptr)) return fail(GEN_EINVAL, "bad output capacity");
+    std::vector<gen_pool_bucket> list;
+    for (size_t i = 0; i < (size_t)pool->n; ++i) {
+        const auto b = bucket_of(*pool, i);
+        auto it = std::find_if(list.begin(), list.end(),
+                               [&](const gen_pool_bucket &x) { return x.n_players == b.first && x.words == b.second; });
+        if (it == list.end()) {
+            gen_pool_bucket x{};
+            x.n_players = b.first;
+            x.words = b.second;
+            const auto pk = packing_of(*pool, i);
+            x.waves_per_group = (int32_t)pk.first;
+            x.waves_per_env = (int32_t)pk.second;
+            list.push_back(x);
+            it = list.end() - 1;
+        }
+        it->n_envs += 1;
     }
+    std::sort(list.begin(), list.end(), [](const gen_pool_bucket &a, const gen_pool_bucket &b) {
+        return a.n_players != b.n_players ? a.n_players < b.n_players : a.words < b.words;
+    });
+    *n_out = (int32_t)list.size();
+    for (int32_t i = 0; i < capacity && i < (int32_t)list.size(); ++i) out[i] = list[(size_t)i];
+    return ok();
+}
+
+int gen_pool_set_buckets(gen_pool *pool, const gen_pool_bucket *table, int32_t n, void *stream)
+{
+    if (pool == nullptr || n < 0 || (n > 0 && table == nullptr)) return fail(GEN_EINVAL, "pool and table are required");
+    for (int32_t i = 0; i < n; ++i) {
+        const gen_pool_bucket &t = table[i];
+        if (t.n_players < 2 || t.n_players > GEN_MAX_PLAYERS || t.words < 1 || t.words > GEN_MAX_CELLS / 64)
+            return fail(GEN_EINVAL, "bucket %d: %d players, %d words is not a bucket", i, t.n_players, t.words);
+        if (t.waves_per_group != 1 && t.waves_per_group != 2 && t.waves_per_group != 4)
+            return fail(GEN_EINVAL, "bucket %d: waves_per_group must be 1, 2 or 4", i);
+        if (t.waves_per_env != 1 && t.waves_per_env != 2)
+            return fail(GEN_EINVAL, "bucket %d: waves_per_env must be 1 or 2", i);
+        if (t.waves_per_env == 2 && t.waves_per_group != 1)
+            return fail(GEN_EINVAL, "bucket %d: two waves per env take a workgroup of their own", i);
+        if (t.reserved[0] || t.reserved[1] || t.reserved[2])
+            return fail(GEN_EINVAL, "bucket %d: reserved must be zero", i);
+        if ((uint64_t)pool->lds_per_wave * (uint64_t)t.waves_per_group > 65536)
+            return fail(GEN_EINVAL, "bucket %d: %d waves per group need more than 64 KiB of LDS", i, t.waves_per_group);
+    }
+    pool->buckets.assign(table, table + n);
+    pool_make_order(*pool);
+    if (pool->d_state) return pool_upload_work(*pool, static_cast<hipStream_t>(stream)) == GEN_OK ? ok() : GEN_EHIP;
     return ok();
 }
 
@@ -761,17 +857,14 @@ int gen_pool_reset(gen_pool *pool, void *d_state, uint64_t state_bytes, uint8_t 
         return fail(GEN_EINVAL, "d_obs must be 16-byte and d_actions 4-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     pool->d_state = d_state;
-    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(d_state) + pool->off_desc, pool->desc.data(),
-                                  pool->desc.size() * sizeof(gen::PoolDesc), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "pool descriptor upload");
-    if (pool_upload_order(*pool, s) != GEN_OK) return GEN_EHIP;
+    if (pool_upload_work(*pool, s) != GEN_OK) return GEN_EHIP;
     gen::PoolArgs a = pool_args(*pool);
+    hipError_t e = hipSuccess;
     a.obs = d_obs;
     a.actions = d_actions;
     a.actor_seed = actor_seed;
     a.actor = d_actions != nullptr ? 1u : 0u;
-    e = gen::launch_pool(a, 1 /* reset */, d_actions != nullptr, (uint32_t)pool->tuning.grid, s);
+    e = gen::launch_pool(a, 1 /* reset */, d_actions != nullptr, (uint32_t)pool->tuning.grid, 1, s);
     if (e != hipSuccess) return hip_fail(e, "pool reset launch");
     return ok();
 }
@@ -791,8 +884,7 @@ int gen_pool_step(gen_pool *pool, int32_t *d_actions, int32_t actor, uint64_t ac
     a.dones = d_dones;
     a.actor_seed = actor_seed;
     a.actor = actor != 0 ? 1u : 0u;
-    hipError_t e = gen::launch_pool(a, 0 /* step */, actor != 0, (uint32_t)pool->tuning.grid,
-                                    static_cast<hipStream_t>(stream));
+    hipError_t e = pool_step_launches(*pool, a, actor != 0, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "pool step launch");
     return ok();
 }
@@ -817,7 +909,7 @@ int gen_pool_capture(gen_pool *pool, int32_t k_steps, int32_t *d_actions, uint64
     a.actor = 1u;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
-    for (int32_t k = 0; k < k_steps && e == hipSuccess; ++k) e = gen::launch_pool(a, 0, true, (uint32_t)pool->tuning.grid, s);
+    for (int32_t k = 0; k < k_steps && e == hipSuccess; ++k) e = pool_step_launches(*pool, a, true, s);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -33,18 +33,26 @@ struct Geom {
     int H, W, HW, S, P, mode, NW;
     uint32_t magic_w;    // ceil(2^20 / W): c / W == (c * magic_w) >> 20 for c < 1024
     uint32_t magic_hw;   // ceil(2^32 / HW): b / HW == (b * magic_hw) >> 32 for b < 65536
-    int obsv;            // observation writer variant (plane alignment)
+    int PS;              // observation plane stride in bytes (HW, or HW padded to 32 bytes)
 };
+
+// Plane stride of a pool env's observation block: H*W rounded up to a
+// multiple of 32 bytes, so every plane starts on its own 32-byte sector and
+// nontemporal stores never write part of a sector another plane shares
+// (measured on the mixed pool: 365 us per step with the unaligned-plane
+// writer, 291 us with planes rounded to 4 bytes, 283 us rounded to 32).
+__host__ __device__ __forceinline__ int pool_plane_stride(int HW) { return (HW + 31) & ~31; }
 
 // Per-env descriptor of a batched pool (32 bytes, device resident).
 struct PoolDesc {
     uint32_t cell_off;   // first cell of the env in the owner/type/army arrays (multiple of 16)
-    uint32_t obs_off16;  // offset of the env's observation block, in 16-byte units
+    uint32_t obs_off16;  // offset of the env's observation block ([P][8] planes of
+                         // pool_plane_stride(H*W) bytes), in 16-byte units
     uint32_t act_off;    // first int32 of the env's actions and rewards
     uint32_t magic_w, magic_hw;
     uint8_t H, W, mode, P;
-    uint8_t cmin, cmax, dmin, obsv;
-    uint32_t reserved;
+    uint8_t cmin, cmax, dmin, pad8;
+    uint32_t env;        // the env's index in the pool (the device array is in work-list order)
 };
 static_assert(sizeof(PoolDesc) == 32, "pool descriptor is 32 bytes");
 

@@ -45,9 +45,9 @@ struct PoolArgs {
     GenParamsDev prm;            // common settings; cities and spawn distance per env
     uint64_t seed, env_base, actor_seed;
     uint32_t n_envs, wpg, lds_per_wave;
+    uint32_t slot_begin, slot_end;    // the segment of the work list this launch steps
     uint32_t actor;              // 1: draw the next actions after the step (ACT kernels)
-    const PoolDesc *desc;
-    const uint32_t *order;       // work list: env of each slot
+    const PoolDesc *desc;        // work list: the descriptor of each slot's env
     EnvScalars *sc;
     int8_t *owner;
     uint8_t *type;
@@ -59,14 +59,13 @@ struct PoolArgs {
 };
 
 // One request of a served batch: one step of a group whose buffers all live
-// in the server's arena (byte offsets from the arena base), and the first
-// workgroup of its envs in the launch.
+// in the server's arena (byte offsets from the arena base).
 struct ServeReq {
-    uint64_t off_desc, off_order, off_sc, off_owner, off_type, off_army;
+    uint64_t off_desc, off_sc, off_owner, off_type, off_army;
     uint64_t off_actions, off_rewards, off_dones, off_obs;
     uint64_t seed, env_base, actor_seed;
     GenParamsDev prm;
-    uint32_t n_envs, actor, wg_begin, pad;
+    uint32_t n_envs, actor;
 };
 
 // One env's block of the feature memory (38-channel features), byte offsets:
@@ -149,14 +148,15 @@ hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream
 // Device address of the static staging array (GEN_STATIC_STAGING_BYTES) on
 // `device`, which must be the current device; looked up once per device.
 hipError_t static_staging(int device, void **out);
-hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, uint32_t grid, hipStream_t stream);
+hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, hipStream_t stream);
 
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);
-hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,
+// Grid (max_envs, n_req): request y's env x per workgroup.
+hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t max_envs, uint32_t lds,
                         hipStream_t stream);
 int obs_variant(int HW, int P);
-hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, hipStream_t stream);
+hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, uint32_t nwv, hipStream_t stream);
 hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream);
 hipError_t launch_reset(const EnvArgs &a, int n_envs, hipStream_t stream);
 hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream);
@@ -189,14 +189,18 @@ struct gen_pool {
     uint64_t seed = 0, env_base = 0;
     int32_t n = 0;
     gen_params common{};
-    std::vector<gen::PoolDesc> desc;
+    std::vector<gen::PoolDesc> desc;      // in env order (the device copy is in work-list order)
     std::vector<uint64_t> work;           // P*H*W per env, for the work order
-    std::vector<uint32_t> order;
-    uint64_t off_scalars = 0, off_desc = 0, off_order = 0, off_owner = 0, off_type = 0, off_army = 0;
+    std::vector<uint32_t> order;          // env of each work-list slot
+    uint64_t off_scalars = 0, off_desc = 0, off_owner = 0, off_type = 0, off_army = 0;
     uint64_t state_bytes = 0, obs_bytes = 0, n_actions = 0;
     uint32_t lds_per_wave = 0;
     int32_t max_cells = 0;
     gen_pool_tuning tuning{1, 0, 0, 0};
+    std::vector<gen_pool_bucket> buckets;  // per-bucket packing (gen_pool_set_buckets); empty = pool-wide
+    // launches of a step: work-list segments [begin, end) sharing a packing
+    struct Segment { uint32_t begin, end, wpg, nwv; };
+    std::vector<Segment> segments;
     void *d_state = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

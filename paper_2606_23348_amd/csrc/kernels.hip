@@ -321,44 +321,52 @@ __device__ __forceinline__ int decode_action(const Lds &L, const Geom &g, int32_
     return src | (dst << 10) | ((k >= 5 ? 1 : 0) << 20);
 }
 
-// Apply player i's decoded move on lane 0, re-validating ownership and army
-// at application time (R4/R5).  Returns the player whose general was
-// captured (-1 if none); the captured general becomes a castle here.
+// Apply player i's decoded move (a wave-uniform value), re-validating
+// ownership and army at application time (R4/R5).  The five LDS values the
+// move can need are read at once and made scalar, the decision runs on the
+// scalar unit, and lane 0 writes the cells that change.  Returns the player
+// whose general was captured (-1 if none); the captured general becomes a
+// castle here.
 __device__ int apply_move(const Lds &L, const Geom &g, const EnvScalars &s, int i, int packed)
 {
     if (packed < 0 || !((s.alive >> i) & 1)) return -1;
-    const int src = packed & 1023, dst = (packed >> 10) & 1023;
+    const int src = packed & 1023, dst = (packed >> 10) & 1023;     // neighbours, never equal
     const bool half = (packed >> 20) & 1;
-    if (L.owner[src] != i) return -1;
-    const int32_t have = L.army[src];
-    if (have <= 1) return -1;
+    const int o_src = readfirst(L.owner[src]);
+    const int32_t have = readfirst(L.army[src]);
+    const int o = readfirst(L.owner[dst]);
+    const int32_t d = readfirst(L.army[dst]);
+    const int t = readfirst(L.type[dst]);
+    if (o_src != i || have <= 1) return -1;
     const int32_t m = half ? (have >> 1) : have - 1;
-    L.army[src] = have - m;
-    const int o = L.owner[dst];
-    const int32_t d = L.army[dst];
+    int o_new = o, victim = -1;
+    int32_t d_new;
     if (o == i) {
-        L.army[dst] = sat_add(d, m);
+        d_new = sat_add(d, m);
     } else if (o >= 0 && is_ally(g.mode, o, i)) {
-        L.army[dst] = sat_add(d, m);
-        L.owner[dst] = (int8_t)i;
+        d_new = sat_add(d, m);
+        o_new = i;
     } else if (m > d) {
-        L.owner[dst] = (int8_t)i;
-        L.army[dst] = m - d;
-        if (L.type[dst] == GENERAL) {
-            int victim = -1;
+        o_new = i;
+        d_new = m - d;
+        if (t == GENERAL) {
 #pragma unroll
             for (int v = 0; v < kMaxP; ++v) {
                 if (v < g.P && victim < 0 && s.gpos[v] == dst && ((s.alive >> v) & 1) && v != i &&
                     !is_ally(g.mode, v, i))
                     victim = v;
             }
-            if (victim >= 0) L.type[dst] = CASTLE;
-            return victim;
         }
     } else {
-        L.army[dst] = d - m;
+        d_new = d - m;
     }
-    return -1;
+    if (lane_id() == 0) {
+        L.army[src] = have - m;
+        L.army[dst] = d_new;
+        L.owner[dst] = (int8_t)o_new;
+        if (victim >= 0) L.type[dst] = CASTLE;
+    }
+    return readfirst(victim);
 }
 
 // All players' moves in rotating priority (reading R5), captures applied at
@@ -372,9 +380,7 @@ __device__ bool resolve_moves(const Lds &L, const Geom &g, EnvScalars &s, int32_
     for (int j = 0; j < g.P; ++j) {
         const int i = (s.turn + j) % g.P;
         const int packed = readlane(my_move, i);
-        int victim = -1;
-        if (lane == 0) victim = apply_move(L, g, s, i, packed);
-        victim = readfirst(victim);
+        const int victim = apply_move(L, g, s, i, packed);
         wave_sync();
         if (victim >= 0) {
             for (int c = lane; c < g.HW; c += kWave) {
@@ -476,9 +482,10 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
 
 // ---------------------------------------------------------------- fused env kernel
 enum { K_STEP = 0, K_RESET = 1, K_OBSERVE = 2 };
-// Observation writers: planes of a multiple of 4 cells (dword aligned) or any
-// other size; OBS_RUNTIME decides per env from the geometry (mixed shapes).
-enum { OBS_QUAD = 0, OBS_STREAM = 1, OBS_RUNTIME = -1 };
+// Observation writers: planes of a multiple of 4 cells (dword aligned), any
+// other size, or planes padded to a multiple of 4 bytes (the layout of a
+// pool's ragged observations, so envs of every shape take the dword writer).
+enum { OBS_QUAD = 0, OBS_STREAM = 1, OBS_PADDED = 2 };
 
 // Player-independent bits of the four cells of quad q, one 0x01 per cell
 // byte (SWAR over the owner and type bytes).
@@ -523,18 +530,23 @@ __device__ __forceinline__ void quad_planes(const Lds &L, const QuadCells &c, ui
 }
 
 // Quad q's dwords of player p's eight planes into the env's observation
-// block ([P][8][HW] bytes), nontemporal.
+// block ([P][8] planes of PS bytes), nontemporal; `keep` masks the bytes of
+// cells past the map in a padded plane's last quad to zero.
 // ro: buffer descriptor of the env's block; the plane offset is a scalar
 // operand and 4q the one vector offset of all eight stores.
+// AUX: the stores' cache policy (nontemporal by default: every plane these
+// stores write starts on a 32-byte sector, so no sector is shared by two
+// planes written at different times).
+template <int AUX = kAuxNT>
 __device__ __forceinline__ void quad_store(const Lds &L, const Geom &g, const Rsrc &ro, const QuadCells &qc,
-                                           uint32_t ac, int p, int q)
+                                           uint32_t ac, int p, int q, int PS, uint32_t keep = ~0u)
 {
     const uint32_t ally = g.mode == MODE_2V2 ? (uint32_t)(p ^ 2) : (uint32_t)p;
     uint32_t v[8];
     quad_planes(L, qc, ac, p, ally, q, v);
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch)
-        __builtin_amdgcn_raw_buffer_store_b32(v[ch], ro, 4 * q, (p * 8 + ch) * g.HW, kAuxNT);
+        __builtin_amdgcn_raw_buffer_store_b32(v[ch] & keep, ro, 4 * q, (p * 8 + ch) * PS, AUX);
 }
 
 // Code bytes of the four cells of quad q for player p (bit k = channel k,
@@ -647,6 +659,27 @@ __device__ __forceinline__ void obs_stream_planes(const Lds &L, const Geom &g, u
     }
 }
 
+// Padded planes (plane stride g.PS, a multiple of 32 bytes): the dword
+// writer for players p_begin .. p_end - 1, quads outer (a quad's cells
+// decoded once for all those players; measured on the mixed pool: 286 ->
+// 273 us per step against players outer); the bytes of cells past the map
+// in a plane's last quads are written as zero.
+__device__ __forceinline__ void obs_padded_planes(const Lds &L, const Geom &g, uint8_t *obs, int p_begin, int p_end)
+{
+    const int lane = lane_id();
+    const int PS = g.PS;
+    const int nq = PS >> 2;
+    const int nfull = ((g.HW + 3) >> 2) - 1;                          // last quad holding map cells
+    const uint32_t tail = (g.HW & 3) ? (1u << (8 * (g.HW & 3))) - 1u : ~0u;
+    const Rsrc ro = buffer_rsrc(obs, (uint32_t)(g.P * 8 * PS));
+    for (int q = lane; q < nq; q += kWave) {
+        const QuadCells qc = quad_cells(L, q);
+        const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[q];
+        const uint32_t keep = q < nfull ? ~0u : q == nfull ? tail : 0u;
+        for (int p = p_begin; p < p_end; ++p) quad_store(L, g, ro, qc, ac, p, q, PS, keep);
+    }
+}
+
 // Per-env inputs and outputs of one step (pointers into this env's rows).
 struct EnvIO {
     EnvScalars *sc;
@@ -667,8 +700,8 @@ struct EnvIO {
 };
 
 // One environment step (or reset / observation) on one wave.  OBSV selects
-// the observation writer at compile time, or at run time from g.obsv when
-// OBSV == OBS_RUNTIME (mixed shapes in one launch).
+// the observation writer and layout at compile time (OBS_PADDED for the
+// mixed shapes of a pool).
 template <int KIND, int OBSV, bool SB, bool ACT>
 __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const GenParamsDev &prm, uint64_t seed,
                                          uint64_t actor_seed, const EnvIO &io)
@@ -868,31 +901,26 @@ __device__ __forceinline__ void env_body(uint8_t *smem, const Geom &g, const Gen
     wave_sync();
     // a second wave of the workgroup (FFA with unaligned planes) waits here
     // for the state and the vision, then writes the later players' planes
-    if (OBSV == OBS_STREAM && io.nwv > 1) __syncthreads();
+    if ((OBSV == OBS_STREAM || OBSV == OBS_PADDED) && io.nwv > 1) __syncthreads();
 
     // Planes of a multiple of 4 cells: each lane takes 4 cells, computes their
     // bytes of all 8 channel planes in registers and stores them directly
     // (4-byte stores, 256 contiguous bytes per wave store).  Other shapes
     // realign the same dwords with lane shuffles below.
-    const bool quad_obs =
-        OBSV == OBS_QUAD || (OBSV == OBS_RUNTIME && (g.HW & 3) == 0);
-    if (quad_obs) {
+    if (OBSV == OBS_QUAD || OBSV == OBS_PADDED) {
         if (io.obs != nullptr) {
-            // Loop order, as measured: quads outer (a quad's owner and type
-            // bits decoded once for all players) in the plain batch kernels,
-            // players outer in the mixed-shape pool, where it was faster.
-            const int nq = g.HW >> 2;
-            const Rsrc ro = buffer_rsrc(io.obs, (uint32_t)(g.P * 8 * g.HW));
+            // Quads outer: a quad's owner and type bits decoded once for
+            // all players.
             if (OBSV == OBS_QUAD) {
+                const int nq = g.HW >> 2;
+                const Rsrc ro = buffer_rsrc(io.obs, (uint32_t)(g.P * 8 * g.HW));
                 for (int q = lane; q < nq; q += kWave) {
                     const QuadCells qc = quad_cells(L, q);
                     const uint32_t ac = reinterpret_cast<const uint32_t *>(L.armyc)[q];
-                    for (int p = 0; p < g.P; ++p) quad_store(L, g, ro, qc, ac, p, q);
+                    for (int p = 0; p < g.P; ++p) quad_store(L, g, ro, qc, ac, p, q, g.HW);
                 }
             } else {
-                for (int p = 0; p < g.P; ++p)
-                    for (int q = lane; q < nq; q += kWave)
-                        quad_store(L, g, ro, quad_cells(L, q), reinterpret_cast<const uint32_t *>(L.armyc)[q], p, q);
+                obs_padded_planes(L, g, io.obs, 0, io.nwv > 1 ? obs_split(g.P) : g.P);
             }
         }
     } else if (io.obs != nullptr) {
@@ -973,20 +1001,24 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB ||
     io.next_actions = a.next_actions + (size_t)e * g.P;
     io.rewards = a.rewards + (size_t)e * g.P;
     io.done = a.dones + e;
-    io.obs = a.obs != nullptr ? a.obs + (size_t)e * (size_t)(g.P * 8 * g.HW) : nullptr;
+    io.obs = a.obs != nullptr ? a.obs + (size_t)e * (size_t)(g.P * 8 * g.PS) : nullptr;
     io.land = a.land + (size_t)e * g.P;
     io.army_tot = a.army_tot + (size_t)e * g.P;
     io.env_id = a.env_base + (uint64_t)e;
     io.actor_step = a.step_idx;
     io.use_tick = false;
     if (NWV > 1) {
-        static_assert(NWV == 1 || OBSV == OBS_STREAM, "a second wave only shares the unaligned-plane writer");
+        static_assert(NWV == 1 || OBSV == OBS_STREAM || OBSV == OBS_PADDED,
+                      "a second wave only shares the unaligned- and padded-plane writers");
         const int wv = readfirst((int)(threadIdx.x >> 6));
         if (wv > 0) {
             // exactly one barrier, matching the one wave 0 passes after the vision
             const Lds L = carve(smem, g);
             __syncthreads();
-            if (io.obs != nullptr) obs_stream_planes(L, g, io.obs, obs_split(g.P), g.P);
+            if (io.obs != nullptr) {
+                if (OBSV == OBS_STREAM) obs_stream_planes(L, g, io.obs, obs_split(g.P), g.P);
+                else obs_padded_planes(L, g, io.obs, obs_split(g.P), g.P);
+            }
             return;
         }
         io.nwv = NWV;
@@ -996,15 +1028,20 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB ||
 
 // ---------------------------------------------------------------- batched pool (mixed shapes)
 // One wave per env, `wpg` envs per workgroup, envs taken in the order of a
-// work list; each env's shape, mode, generator settings and buffer offsets
-// come from its 32-byte descriptor.  With a grid smaller than the work list
-// the workgroups loop (persistent form).
-// One pool env on the calling wave (slot = position in the work list).
+// work list (slots slot_begin .. slot_end - 1 of it: a launch covers one
+// segment of envs that share a packing); each env's shape, mode, generator
+// settings and buffer offsets come from its 32-byte descriptor.  With a
+// grid smaller than the segment the workgroups loop (persistent form).
+// With two waves per env (NWV = 2, one env per workgroup) the second wave
+// writes the observation planes of the later players, as in the plain
+// two-wave step.
+// One pool env on the calling wave (slot = position in the work list;
+// wave = the wave's index within the env, of nwv).
 template <int KIND, bool ACT>
-__device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint32_t slot)
+__device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint32_t slot, int nwv = 1, int wave = 0)
 {
-    const uint32_t e = a.order[slot];
-    const PoolDesc d = a.desc[e];
+    const PoolDesc d = a.desc[slot];
+    const uint32_t e = d.env;
     Geom g;
     g.H = d.H;
     g.W = d.W;
@@ -1015,7 +1052,15 @@ __device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint3
     g.NW = (g.HW + 63) >> 6;
     g.magic_w = d.magic_w;
     g.magic_hw = d.magic_hw;
-    g.obsv = d.obsv;
+    g.PS = pool_plane_stride(g.HW);
+    uint8_t *obs = a.obs != nullptr ? a.obs + (size_t)d.obs_off16 * 16 : nullptr;
+    if (wave > 0) {
+        // exactly one barrier, matching the one wave 0 passes after the vision
+        const Lds L = carve(smem, g);
+        __syncthreads();
+        if (obs != nullptr) obs_padded_planes(L, g, obs, obs_split(g.P), g.P);
+        return;
+    }
     GenParamsDev prm = a.prm;
     prm.cmin = d.cmin;
     prm.cmax = d.cmax;
@@ -1029,30 +1074,39 @@ __device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint3
     io.next_actions = a.actor ? a.actions + d.act_off : nullptr;
     io.rewards = a.rewards + d.act_off;
     io.done = a.dones + e;
-    io.obs = a.obs != nullptr ? a.obs + (size_t)d.obs_off16 * 16 : nullptr;
+    io.obs = obs;
     io.land = nullptr;
     io.army_tot = nullptr;
     io.env_id = a.env_base + e;
     io.actor_step = 0;
     io.use_tick = true;
-    env_body<KIND, OBS_RUNTIME, false, ACT>(smem, g, prm, a.seed, a.actor_seed, io);
+    io.nwv = nwv;
+    env_body<KIND, OBS_PADDED, false, ACT>(smem, g, prm, a.seed, a.actor_seed, io);
 }
 
-// PERSIST = false: one env per wave, the grid covers the work list.
-// PERSIST = true: a smaller grid whose waves stride over the work list.
-template <int KIND, bool ACT, bool PERSIST>
+// PERSIST = false: one env per wave (per workgroup with NWV = 2), the grid
+// covers the segment.  PERSIST = true (NWV = 1 only: the two waves of an env
+// would need a second barrier before reusing the LDS for the next env): a
+// smaller grid whose waves stride over the segment.
+template <int KIND, bool ACT, bool PERSIST, int NWV>
 __global__ __launch_bounds__(256) void k_pool(PoolArgs a)
 {
+    static_assert(NWV == 1 || !PERSIST, "two waves per env only in the one-shot grid");
     extern __shared__ __align__(16) uint8_t smem[];
     // wave index as a scalar: everything derived from the env id stays wave-uniform
     const uint32_t wave = (uint32_t)readfirst((int)(threadIdx.x >> 6));
+    if (NWV == 2) {
+        const uint32_t slot = a.slot_begin + blockIdx.x;
+        if (slot < a.slot_end) pool_env<KIND, ACT>(a, smem, slot, 2, (int)wave);
+        return;
+    }
     uint8_t *mine = smem + wave * a.lds_per_wave;
     if (PERSIST) {
-        for (uint32_t slot = blockIdx.x * a.wpg + wave; slot < a.n_envs; slot += gridDim.x * a.wpg)
+        for (uint32_t slot = a.slot_begin + blockIdx.x * a.wpg + wave; slot < a.slot_end; slot += gridDim.x * a.wpg)
             pool_env<KIND, ACT>(a, mine, slot);
     } else {
-        const uint32_t slot = blockIdx.x * a.wpg + wave;
-        if (slot < a.n_envs) pool_env<KIND, ACT>(a, mine, slot);
+        const uint32_t slot = a.slot_begin + blockIdx.x * a.wpg + wave;
+        if (slot < a.slot_end) pool_env<KIND, ACT>(a, mine, slot);
     }
 }
 
@@ -1107,6 +1161,18 @@ static hipError_t launch_kind(const EnvArgs &a, int n_envs, hipStream_t stream)
 {
     const dim3 grid((unsigned)n_envs), block(kWave);
     const uint32_t lds = lds_bytes(a.g);
+    if (a.g.PS != a.g.HW) {
+        // planes padded to 32 bytes: the dword writer for every shape; more
+        // than 4 players share it between two waves, as the unaligned writer
+        if constexpr (KIND == K_STEP) {
+            if (a.g.P > 4 && a.obs != nullptr && n_envs <= 16384) {
+                hipLaunchKernelGGL((k_env<KIND, OBS_PADDED, SB, ACT, 2>), grid, dim3(2 * kWave), lds, stream, a);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_env<KIND, OBS_PADDED, SB, ACT, 1>), grid, block, lds, stream, a);
+        return hipGetLastError();
+    }
     switch (obs_variant(a.g)) {
     case OBS_QUAD: hipLaunchKernelGGL((k_env<KIND, OBS_QUAD, SB, ACT, 1>), grid, block, lds, stream, a); break;
     default:
@@ -1148,32 +1214,30 @@ hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 
 // ---------------------------------------------------------------- served batches
 // One launch steps the envs of many requests (each request = one step of a
-// group, a pool of its own).  Workgroup w belongs to the request r with
-// reqs[r].wg_begin <= w < reqs[r + 1].wg_begin, found by a binary search over
-// the request table (wave-uniform loads).
+// group, a pool of its own).  The grid is (largest request's env count) x
+// (requests): workgroup (x, y) steps env x of request y, or exits at once
+// when request y has fewer envs -- one wave-uniform load of the request
+// instead of a search over the table.
 // Buffers are addressed as arena + offset so that every pointer derives from
 // a kernel argument (global address space, scalar base + vector offset).
-__global__ __launch_bounds__(64) void k_serve(uint8_t *arena, const ServeReq *__restrict__ reqs, uint32_t n_req)
+__global__ __launch_bounds__(64) void k_serve(uint8_t *arena, const ServeReq *__restrict__ reqs)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t w = blockIdx.x;
-    uint32_t lo = 0, hi = n_req;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (reqs[mid].wg_begin <= w) lo = mid; else hi = mid;
-    }
-    const ServeReq &r = reqs[readfirst((int)lo)];
+    const ServeReq &r = reqs[blockIdx.y];
+    const uint32_t slot = blockIdx.x;
+    if (slot >= r.n_envs) return;
     PoolArgs a;
     a.prm = r.prm;
     a.seed = r.seed;
     a.env_base = r.env_base;
     a.actor_seed = r.actor_seed;
     a.n_envs = r.n_envs;
+    a.slot_begin = 0;
+    a.slot_end = r.n_envs;
     a.wpg = 1;
     a.lds_per_wave = 0;
     a.actor = r.actor;
     a.desc = reinterpret_cast<const PoolDesc *>(arena + r.off_desc);
-    a.order = reinterpret_cast<const uint32_t *>(arena + r.off_order);
     a.sc = reinterpret_cast<EnvScalars *>(arena + r.off_sc);
     a.owner = reinterpret_cast<int8_t *>(arena + r.off_owner);
     a.type = arena + r.off_type;
@@ -1182,41 +1246,43 @@ __global__ __launch_bounds__(64) void k_serve(uint8_t *arena, const ServeReq *__
     a.rewards = reinterpret_cast<int32_t *>(arena + r.off_rewards);
     a.dones = arena + r.off_dones;
     a.obs = r.off_obs != ~0ull ? arena + r.off_obs : nullptr;
-    const uint32_t slot = w - r.wg_begin;
-    if (slot < a.n_envs) pool_env<K_STEP, true>(a, smem, slot);
+    pool_env<K_STEP, true>(a, smem, slot);
 }
 
-hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t n_wg, uint32_t lds,
+hipError_t launch_serve(uint8_t *arena, const ServeReq *d_reqs, uint32_t n_req, uint32_t max_envs, uint32_t lds,
                         hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_serve, dim3(n_wg), dim3(kWave), lds, stream, arena, d_reqs, n_req);
+    hipLaunchKernelGGL(k_serve, dim3(max_envs, n_req), dim3(kWave), lds, stream, arena, d_reqs);
     return hipGetLastError();
 }
 
-template <int KIND, bool ACT, bool PERSIST>
+template <int KIND, bool ACT, bool PERSIST, int NWV>
 static hipError_t launch_pool_kind(const PoolArgs &a, uint32_t grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_pool<KIND, ACT, PERSIST>), dim3(grid), dim3(kWave * a.wpg), a.lds_per_wave * a.wpg,
-                       stream, a);
+    const uint32_t threads = NWV == 2 ? 2 * kWave : kWave * a.wpg;
+    const uint32_t lds = NWV == 2 ? a.lds_per_wave : a.lds_per_wave * a.wpg;
+    hipLaunchKernelGGL((k_pool<KIND, ACT, PERSIST, NWV>), dim3(grid), dim3(threads), lds, stream, a);
     return hipGetLastError();
 }
 
-// grid == 0: one wave per env (ceil(n_envs / wpg) workgroups); else persistent.
-hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, hipStream_t stream)
+template <int KIND, bool ACT>
+static hipError_t launch_pool_act(const PoolArgs &a, uint32_t grid, uint32_t nwv, hipStream_t stream)
 {
-    const uint32_t full = (a.n_envs + a.wpg - 1) / a.wpg;
-    if (grid == 0 || grid >= full) {
-        if (kind == K_RESET)
-            return act ? launch_pool_kind<K_RESET, true, false>(a, full, stream)
-                       : launch_pool_kind<K_RESET, false, false>(a, full, stream);
-        return act ? launch_pool_kind<K_STEP, true, false>(a, full, stream)
-                   : launch_pool_kind<K_STEP, false, false>(a, full, stream);
-    }
+    const uint32_t n = a.slot_end - a.slot_begin;
+    if (nwv == 2) return launch_pool_kind<KIND, ACT, false, 2>(a, n, stream);
+    const uint32_t full = (n + a.wpg - 1) / a.wpg;
+    if (grid == 0 || grid >= full) return launch_pool_kind<KIND, ACT, false, 1>(a, full, stream);
+    return launch_pool_kind<KIND, ACT, true, 1>(a, grid, stream);
+}
+
+// One segment of the work list [a.slot_begin, a.slot_end): grid == 0 one
+// wave (nwv waves) per env, else persistent (nwv == 1 only).
+hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, uint32_t nwv, hipStream_t stream)
+{
+    if (a.slot_end <= a.slot_begin) return hipSuccess;
     if (kind == K_RESET)
-        return act ? launch_pool_kind<K_RESET, true, true>(a, grid, stream)
-                   : launch_pool_kind<K_RESET, false, true>(a, grid, stream);
-    return act ? launch_pool_kind<K_STEP, true, true>(a, grid, stream)
-               : launch_pool_kind<K_STEP, false, true>(a, grid, stream);
+        return act ? launch_pool_act<K_RESET, true>(a, grid, 1, stream) : launch_pool_act<K_RESET, false>(a, grid, 1, stream);
+    return act ? launch_pool_act<K_STEP, true>(a, grid, nwv, stream) : launch_pool_act<K_STEP, false>(a, grid, nwv, stream);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int n_envs, hipStream_t stream)

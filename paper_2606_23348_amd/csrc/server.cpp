@@ -229,12 +229,11 @@ void complete_slot(gen_server &s, Slot &sl, int status)
     sl.busy = false;
 }
 
-void fill_req(const gen_server &s, const Group &g, uint32_t wg_begin, gen::ServeReq *r)
+void fill_req(const gen_server &s, const Group &g, gen::ServeReq *r)
 {
     const gen_pool &pl = *g.pool;
     std::memset(r, 0, sizeof *r);
     r->off_desc = g.off_state + pl.off_desc;
-    r->off_order = g.off_state + pl.off_order;
     r->off_sc = g.off_state + pl.off_scalars;
     r->off_owner = g.off_state + pl.off_owner;
     r->off_type = g.off_state + pl.off_type;
@@ -249,7 +248,6 @@ void fill_req(const gen_server &s, const Group &g, uint32_t wg_begin, gen::Serve
     r->prm = gen::prm_of(pl.common);
     r->n_envs = (uint32_t)pl.n;
     r->actor = g.actor ? 1u : 0u;
-    r->wg_begin = wg_begin;
     (void)s;
 }
 
@@ -444,7 +442,7 @@ void scheduler(gen_server *sp)
         uint32_t n_req = 0;
         if (launch_now) {
             Slot &sl = *free_slot;
-            uint32_t wg = 0, lds = 0;
+            uint32_t wg = 0, lds = 0, max_envs = 0;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
                 auto tk = s.tickets.find(*it);
                 if (tk == s.tickets.end() || tk->second.status != 1) {
@@ -462,9 +460,10 @@ void scheduler(gen_server *sp)
                 Group &g = *gi->second;
                 if (g.busy || (s.max_batch_envs && n_req > 0 && wg + (uint32_t)g.n_envs > s.max_batch_envs)) { ++it; continue; }
                 g.busy = true;
-                fill_req(s, g, wg, &sl.h_table[n_req]);
+                fill_req(s, g, &sl.h_table[n_req]);
                 sl.reqs.emplace_back(*it, g.id);
                 wg += (uint32_t)g.n_envs;
+                max_envs = std::max(max_envs, (uint32_t)g.n_envs);
                 lds = std::max(lds, g.pool->lds_per_wave);
                 ++n_req;
                 it = s.queue.erase(it);
@@ -479,7 +478,7 @@ void scheduler(gen_server *sp)
                 lk.unlock();
                 hipError_t e = hipMemcpyAsync(d_table, sl.h_table, n_req * sizeof(gen::ServeReq),
                                               hipMemcpyHostToDevice, sl.stream);
-                if (e == hipSuccess) e = gen::launch_serve(s.arena, d_table, n_req, wg, lds, sl.stream);
+                if (e == hipSuccess) e = gen::launch_serve(s.arena, d_table, n_req, max_envs, lds, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
                 if (e != hipSuccess) {
                     lk.lock();

@@ -9,6 +9,13 @@ cached per (GPU architecture, pool signature) in a JSON file.
 
     best, table = tune(specs, common, seed=4, actor_seed=1004)
     pool.set_tuning(**best)
+
+tune_buckets() then chooses a packing per size bucket (players, 64-cell
+words): envs per workgroup and one or two waves per env, timed bucket by
+bucket, verified on the whole pool the same way:
+
+    buckets, report = tune_buckets(specs, common, seed=4, actor_seed=1004, base=best)
+    pool.set_buckets(buckets)
 """
 from __future__ import annotations
 
@@ -102,3 +109,90 @@ def tune(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, steps: in
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return best, table
+
+
+BUCKET_CANDIDATES = ({"waves_per_group": 1, "waves_per_env": 1}, {"waves_per_group": 2, "waves_per_env": 1},
+                     {"waves_per_group": 4, "waves_per_env": 1}, {"waves_per_group": 1, "waves_per_env": 2})
+
+
+def _time_steps(pool: Pool, actor_seed: int, steps: int, warmup: int, stream) -> float:
+    import torch
+    for _ in range(warmup):
+        pool.step(actor_seed=actor_seed, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        pool.step(actor_seed=actor_seed, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / steps
+
+
+def tune_buckets(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, base: dict | None = None,
+                 steps: int = 10, warmup: int = 3, verify_steps: int = 3, min_envs: int = 2048,
+                 cache_path: str | None = DEFAULT_CACHE, force: bool = False, progress=None):
+    """Per-bucket packing: each size bucket (players, 64-cell words) of the
+    pool with at least min_envs envs is timed on its own, as a pool of just
+    its envs, under every candidate of BUCKET_CANDIDATES (envs per
+    workgroup, one or two waves per env); the fastest is kept for it, the
+    other buckets keep the pool-wide packing `base`.  The table is accepted
+    only if the whole pool, from the same reset, gives bit-identical results
+    under it and under `base`.  Returns (table, report) where report holds
+    every candidate's time per bucket.  Cached per (architecture, pool
+    signature)."""
+    import torch
+    base = dict(base or {"waves_per_group": 1, "grid": 0, "order": 0})
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    key = f"{arch}/{signature(specs)}/buckets/{json.dumps(base, sort_keys=True)}"
+    if cache_path and not force and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]["table"], cache[key]["report"]
+    stream = torch.cuda.current_stream()
+    full = Pool(specs, common, seed=seed)
+    full.set_tuning(**base, stream=stream)
+    buckets = full.buckets()
+    P = np.asarray(specs["P"], np.int64)
+    words = (np.asarray(specs["H"], np.int64) * np.asarray(specs["W"], np.int64) + 63) // 64
+    table, report = [], {}
+    for b in buckets:
+        if b["n_envs"] < min_envs:
+            continue
+        idx = np.flatnonzero((P == b["n_players"]) & (words == b["words"]))
+        sub = Pool({k: np.asarray(specs[k])[idx] for k in SPEC_FIELDS}, common, seed=seed)
+        sub.set_tuning(**base, stream=stream)
+        times = {}
+        for c in BUCKET_CANDIDATES:
+            entry = dict(n_players=b["n_players"], words=b["words"], **c)
+            try:
+                sub.set_buckets([entry], stream=stream)
+            except GenError:
+                times[json.dumps(c, sort_keys=True)] = None      # does not fit (LDS)
+                continue
+            sub.reset(actor_seed=actor_seed, stream=stream)
+            times[json.dumps(c, sort_keys=True)] = _time_steps(sub, actor_seed, steps, warmup, stream)
+        name = f"P{b['n_players']}-w{b['words']}"
+        report[name] = {"n_envs": b["n_envs"], "us": times}
+        best = min((k for k in times if times[k] is not None), key=times.get)
+        table.append(dict(n_players=b["n_players"], words=b["words"], **json.loads(best)))
+        if progress is not None:
+            progress(f"tune bucket {name} ({b['n_envs']} envs): best {best} {times[best]:.1f} us")
+        del sub
+    # the table must not change any result
+    _run_from_reset(full, actor_seed, verify_steps, stream)
+    ref = full.digest()
+    full.set_buckets(table, stream=stream)
+    _run_from_reset(full, actor_seed, verify_steps, stream)
+    if full.digest() != ref:
+        raise RuntimeError("the per-bucket packing changed the results")
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = {"table": table, "report": report}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return table, report

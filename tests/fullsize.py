@@ -43,8 +43,11 @@ class PlainShards:
     shard's first env), stepped in parallel; compares against the GPU's
     full host-format state, observation, rewards, dones and actions."""
 
-    def __init__(self, cfg_kw: dict, E: int, pool: ThreadPoolExecutor, n_shards: int | None = None):
+    def __init__(self, cfg_kw: dict, E: int, pool: ThreadPoolExecutor, n_shards: int | None = None,
+                 plane_stride: int | None = None):
         n = n_shards or 4 * pool._max_workers
+        self.HW = cfg_kw["H"] * cfg_kw["W"]
+        self.PS = plane_stride or self.HW      # GPU observation planes of PS bytes (padded if > H*W)
         self.bounds = np.linspace(0, E, min(n, E) + 1).astype(np.int64)
         self.pool = pool
         self.cfgs = [oracle.Config(env_base=int(lo), **cfg_kw) for lo in self.bounds[:-1]]
@@ -67,10 +70,22 @@ class PlainShards:
             return None
         self._each(one)
 
+    def _obs_mismatch(self, got_obs: np.ndarray, i: int) -> str | None:
+        """Shard i's observation against the oracle's ([E, P, 8, H, W] on the
+        GPU side, or [E, P, 8, PS] with zero padding after each plane)."""
+        lo, hi = self.bounds[i], self.bounds[i + 1]
+        want = oracle.observe(self.cfgs[i], self.states[i])
+        g = got_obs[lo:hi]
+        if self.PS != self.HW:
+            if g[..., self.HW:].any():
+                return "nonzero plane padding"
+            g = np.ascontiguousarray(g[..., :self.HW]).reshape(want.shape)
+        return first_mismatch(g, want)
+
     def check_obs(self, got_obs: np.ndarray, where: str):
         def one(i):
             lo, hi = self.bounds[i], self.bounds[i + 1]
-            m = first_mismatch(got_obs[lo:hi], oracle.observe(self.cfgs[i], self.states[i]))
+            m = self._obs_mismatch(got_obs, i)
             return f"{where}: observation of envs {lo}..{hi - 1}: {m}" if m else None
         self._each(one)
 
@@ -98,7 +113,7 @@ class PlainShards:
                 m = first_mismatch(g, w)
                 if m:
                     return f"{where}: {name} of envs {lo}..{hi - 1}: {m}"
-            m = first_mismatch(got_obs[lo:hi], oracle.observe(self.cfgs[i], self.states[i]))
+            m = self._obs_mismatch(got_obs, i)
             if m:
                 return f"{where}: observation of envs {lo}..{hi - 1}: {m}"
             return None
@@ -136,7 +151,7 @@ class PoolBuckets:
             cfg = oracle.Config(H=H, W=W, mode=mode, P=P, cities_min=cmin, cities_max=cmax, min_general_dist=dmin,
                                 seed=seed, env_ids=(np.uint64(env_base) + idx.astype(np.uint64)), **common_kw)
             self.buckets.append({"idx": idx, "cfg": cfg, "cells": cell_off[idx], "obs": obs_off[idx].astype(np.int64),
-                                 "act": act_off[idx].astype(np.int64), "HW": H * W, "P": P})
+                                 "act": act_off[idx].astype(np.int64), "HW": H * W, "PS": (H * W + 31) & ~31, "P": P})
         self.states = list(pool.map(lambda bk: oracle.reset(bk["cfg"], len(bk["idx"]))[0], self.buckets))
         self.next_act: list[np.ndarray | None] = [None] * len(self.buckets)
 
@@ -171,12 +186,24 @@ class PoolBuckets:
             return None
         self._each(one)
 
+    def _obs_check(self, b: int, got_obs: np.ndarray) -> str | None:
+        """Bucket b's observations: each env's block is [P][8] planes of PS
+        bytes, the map's H*W bytes then zero padding."""
+        bk = self.buckets[b]
+        n, P, HW, PS = len(bk["idx"]), bk["P"], bk["HW"], bk["PS"]
+        got = self._rows(got_obs, bk["obs"], P * 8 * PS).reshape(n, P * 8, PS)
+        want = oracle.observe(bk["cfg"], self.states[b]).reshape(n, P * 8, HW)
+        m = first_mismatch(got[:, :, :HW], want)
+        if m:
+            return f"{self._where(b)} observation: {m}"
+        if PS > HW and got[:, :, HW:].any():
+            return f"{self._where(b)} observation: nonzero plane padding"
+        return None
+
     def check_obs(self, got_obs: np.ndarray, where: str):
         def one(b):
-            bk = self.buckets[b]
-            want = oracle.observe(bk["cfg"], self.states[b]).reshape(len(bk["idx"]), -1)
-            m = first_mismatch(self._rows(got_obs, bk["obs"], want.shape[1]), want)
-            return f"{where}: {self._where(b)} observation: {m}" if m else None
+            m = self._obs_check(b, got_obs)
+            return f"{where}: {m}" if m else None
         self._each(one)
 
     def env_state(self, e: int) -> tuple:
@@ -208,11 +235,8 @@ class PoolBuckets:
             m = first_mismatch(self._rows(got_rew, bk["act"], bk["P"]), r) or first_mismatch(got_done[bk["idx"]], d)
             if m:
                 return f"{where}: {self._where(b)} rewards/dones: {m}"
-            want = oracle.observe(bk["cfg"], st).reshape(len(bk["idx"]), -1)
-            m = first_mismatch(self._rows(got_obs, bk["obs"], want.shape[1]), want)
-            if m:
-                return f"{where}: {self._where(b)} observation: {m}"
-            return None
+            m = self._obs_check(b, got_obs)
+            return f"{where}: {m}" if m else None
         self._each(one)
 
     def n_done_episodes(self) -> int:

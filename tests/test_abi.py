@@ -141,7 +141,7 @@ def test_pool_plan_host_side(L):
     obs = np.zeros(3, np.uint64)
     act = np.zeros(3, np.uint32)
     assert L.gen_pool_offsets(h, obs.ctypes.data, act.ctypes.data) == 0
-    sizes = [2 * 8 * 120, 4 * 8 * 625, 3 * 8 * 9]
+    sizes = [2 * 8 * 128, 4 * 8 * 640, 3 * 8 * 32]      # planes padded to a multiple of 32 bytes
     assert obs.tolist() == [0, (sizes[0] + 15) // 16 * 16, ((sizes[0] + 15) // 16 + (sizes[1] + 15) // 16) * 16]
     assert act.tolist() == [0, 2, 6]
     assert info.obs_bytes == sum((s + 15) // 16 * 16 for s in sizes)
@@ -161,3 +161,31 @@ def test_pool_rejects_bad_spec(L):
     with pytest.raises(gen.GenError) as ei:
         gen.gen_pool_create(1, 0, specs)
     assert "env spec 1" in str(ei.value)
+
+
+def test_pool_buckets_host_side(L):
+    """Size buckets (players, 64-cell words) of a pool and their packing,
+    listed and set on the host (no device needed before a pool is bound)."""
+    import numpy as np
+    specs = {"H": np.array([10, 25, 3, 10, 25]), "W": np.array([12, 25, 3, 13, 24]), "mode": np.array([0, 1, 2, 0, 1]),
+             "P": np.array([2, 4, 3, 2, 4]), "cities_min": np.array([2, 8, 0, 2, 8]),
+             "cities_max": np.array([3, 13, 1, 3, 13]), "min_general_dist": np.array([9, 6, 1, 9, 6])}
+    h = gen.gen_pool_create(5, 0, specs)
+    n = ctypes.c_int32()
+    assert L.gen_pool_buckets(h, None, 0, ctypes.byref(n)) == 0 and n.value == 4
+    arr = (gen.gen_pool_bucket * 4)()
+    assert L.gen_pool_buckets(h, arr, 4, ctypes.byref(n)) == 0
+    got = [(b.n_players, b.words, b.n_envs, b.waves_per_group, b.waves_per_env) for b in arr]
+    # 10x12 takes 2 words, 10x13 3, 25x25 and 25x24 10, 3x3 1; in order of players, then words
+    assert got == [(2, 2, 1, 1, 1), (2, 3, 1, 1, 1), (3, 1, 1, 1, 1), (4, 10, 2, 1, 1)]
+    table = (gen.gen_pool_bucket * 2)(gen.gen_pool_bucket(4, 10, 0, 1, 2), gen.gen_pool_bucket(2, 2, 0, 2, 1))
+    assert L.gen_pool_set_buckets(h, table, 2, None) == 0
+    assert L.gen_pool_buckets(h, arr, 4, ctypes.byref(n)) == 0
+    packing = {(b.n_players, b.words): (b.waves_per_group, b.waves_per_env) for b in arr[:n.value]}
+    assert packing[(4, 10)] == (1, 2) and packing[(2, 2)] == (2, 1)
+    bad = (gen.gen_pool_bucket * 1)(gen.gen_pool_bucket(4, 10, 0, 2, 2))   # two waves per env need their own group
+    assert L.gen_pool_set_buckets(h, bad, 1, None) == gen.GEN_EINVAL
+    bad = (gen.gen_pool_bucket * 1)(gen.gen_pool_bucket(9, 10, 0, 1, 1))
+    assert L.gen_pool_set_buckets(h, bad, 1, None) == gen.GEN_EINVAL
+    assert L.gen_pool_set_buckets(h, None, 0, None) == 0
+    assert L.gen_pool_destroy(h) == 0

@@ -40,20 +40,22 @@ def _progress(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("name,steps_all,steps_total", [("c2", 200, 500), ("c3", 100, 300)])
-def test_plain_workload_every_env(gen, name, steps_all, steps_total):
+@pytest.mark.parametrize("name,steps_all,steps_total,obs_layout",
+                         [("c2", 200, 500, 0), ("c3", 100, 300, 1), ("c3", 30, 60, 0)],
+                         ids=["c2", "c3-padded", "c3-dense"])
+def test_plain_workload_every_env(gen, name, steps_all, steps_total, obs_layout):
     """gen_step_sample (the launch bench.py times) on the full workload:
     every env every step for steps_all steps, then the strided subset."""
     import torch
     wl = workloads.PLAIN[name]
     prm = wl.params()
     E, P = wl.n_envs, wl.P
-    b = gen.Batch(E, wl.H, wl.W, wl.mode, gen.make_params(wl.mode, P, **prm), seed=wl.seed)
+    b = gen.Batch(E, wl.H, wl.W, wl.mode, gen.make_params(wl.mode, P, obs_layout=obs_layout, **prm), seed=wl.seed)
     cfg_kw = dict(H=wl.H, W=wl.W, mode=wl.mode, P=P, seed=wl.seed,
                   **{k: v for k, v in prm.items() if k != "n_players"})
     obs_host = torch.empty(tuple(b.obs.shape), dtype=torch.uint8, pin_memory=True)
     with ThreadPoolExecutor(host_threads()) as pool:
-        sh = PlainShards(cfg_kw, E, pool)
+        sh = PlainShards(cfg_kw, E, pool, plane_stride=b.PS)
         torch.cuda.synchronize()
         sh.check_state(b.get_state(), f"{name} reset")
         obs_host.copy_(b.obs)
@@ -78,6 +80,9 @@ def test_plain_workload_every_env(gen, name, steps_all, steps_total):
         b.step_sample(wl.actor_seed, t + 1)
         gst = b.get_envs(ids)
         gobs = b.obs[idx_dev].cpu().numpy()
+        if b.padded:
+            assert not gobs[..., b.H * b.W:].any(), f"{name} step {t}: nonzero plane padding"
+            gobs = np.ascontiguousarray(gobs[..., :b.H * b.W]).reshape(len(ids), P, 8, wl.H, wl.W)
         gact, grew, gdone = b.actions.cpu().numpy(), b.rewards.cpu().numpy(), b.dones.cpu().numpy()
         for j, (c, s) in enumerate(subs):
             e = int(ids[j])
@@ -139,9 +144,9 @@ def test_pool_workload_every_env(gen):
                 for k in KEYS:
                     m = first_mismatch(got[k], st[k])
                     assert m is None, f"{where} field {k}: {m}"
-                o = int(pl.obs_off[e])
                 want = oracle.observe(c, st)
-                assert np.array_equal(obs[o:o + want.size].reshape(want.shape), want), where + " observation"
+                got_o = gen.pool_env_obs(obs, int(pl.obs_off[e]), c.H, c.W, c.P).reshape(want.shape)
+                assert np.array_equal(got_o, want), where + " observation"
                 assert np.array_equal(act[pl.env_slice(e)], oracle.sample(c, st, wl.actor_seed, t + 1)[0]), where
 
 

@@ -50,20 +50,30 @@ def assert_obs_equal(got, want, where=""):
         raise AssertionError(f"{where}: obs differs at {len(bad)} places, first {bad[:5].tolist()}")
 
 
+def gpu_obs(b):
+    """The batch's observation as uint8 [E, P, 8, H, W]; with padded planes
+    (obs_layout 1) also checks that the padding bytes are zero."""
+    if b.padded:
+        raw = b.obs.cpu().numpy()
+        assert not raw[..., b.H * b.W:].any(), "nonzero plane padding"
+    return b.obs_dense()
+
+
 def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=1, scoreboard=False,
-               fused=False):
+               fused=False, obs_layout=0):
     """Step E envs on both sides for `steps` steps with the random actor;
     compare actions, rewards, dones, observations and full state.  With
     fused=True the GPU runs gen_step_sample (step + next actions in one
-    launch) and its actions are compared with the oracle's next draw."""
+    launch) and its actions are compared with the oracle's next draw.
+    obs_layout=1: the GPU writes planes padded to 32 bytes."""
     import torch
-    params = gparams(gen, mode, P, prm)
+    params = gparams(gen, mode, P, dict(prm, obs_layout=obs_layout))
     b = gen.Batch(E, H, W, mode, params, seed=seed, scoreboard=scoreboard)
     cfg = ocfg(H, W, mode, P, seed, **prm)
     ost, att = oracle.reset(cfg, E)
     torch.cuda.synchronize()
     assert_state_equal(b.get_state(), ost, "reset")
-    assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), "reset obs")
+    assert_obs_equal(gpu_obs(b), oracle.observe(cfg, ost), "reset obs")
     n_done = 0
     if fused:
         b.sample(actor_seed, 0)
@@ -84,7 +94,7 @@ def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=
                     where + " next actions"
             assert np.array_equal(b.rewards.cpu().numpy(), orew), where + " rewards"
             assert np.array_equal(b.dones.cpu().numpy(), odone), where + " dones"
-            assert_obs_equal(b.obs.cpu().numpy(), oracle.observe(cfg, ost), where)
+            assert_obs_equal(gpu_obs(b), oracle.observe(cfg, ost), where)
             assert_state_equal(b.get_state(), ost, where)
             if scoreboard:
                 land, army = oracle.scoreboard(cfg, ost)
@@ -150,6 +160,34 @@ def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
                cities_max=min(6, H * W // 4), min_general_dist=min(5, (H + W) // 3), auto_reset=1)
     run_parity(gen, H, W, mode, P, E, steps, seed=H * 7 + W, actor_seed=99, prm=prm, check_every=1, fused=fused)
+
+
+@pytest.mark.parametrize("H,W,mode,P,E,steps", [
+    (25, 25, 2, 8, 24, 200),     # FFA-8: two waves per env share the padded planes
+    (13, 9, 2, 7, 20, 150),      # FFA-7, two waves (2 and 5 players' planes)
+    (7, 9, 2, 3, 37, 300),       # one wave, H*W = 3 mod 4
+    (17, 18, 0, 2, 24, 150),     # H*W = 2 mod 4
+    (31, 31, 1, 4, 8, 100),      # 2v2, H*W = 1 mod 4
+    (3, 3, 0, 2, 64, 200),       # tiny grid: one quad of map cells, seven of padding
+    (8, 4, 0, 2, 16, 100),       # H*W = 32: padded and dense layouts coincide
+])
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_trajectory_parity_padded_planes(gen, H, W, mode, P, E, steps, fused):
+    """obs_layout 1 (planes padded to 32 bytes, every plane written by the
+    dword writer): the same observation bytes, zero padding."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
+               cities_max=min(6, H * W // 4), min_general_dist=min(5, (H + W) // 3), auto_reset=1)
+    run_parity(gen, H, W, mode, P, E, steps, seed=H * 11 + W, actor_seed=98, prm=prm, check_every=1, fused=fused,
+               obs_layout=1)
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_two_wave_padded_regenerates_maps(gen, fused):
+    """Two waves per env on padded planes with many episode ends (5x5 FFA-5)."""
+    prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=0, cities_max=1, min_general_dist=2,
+               auto_reset=1)
+    n = run_parity(gen, 5, 5, 2, 5, 64, 500, seed=43, actor_seed=44, prm=prm, fused=fused, obs_layout=1)
+    assert n > 10
 
 
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])

@@ -53,10 +53,13 @@ def check_env(pool, e, cfg, ost, obs_cpu, act_cpu, where, next_act=None):
     got = pool.get_env(e)
     for k in KEYS:
         assert np.array_equal(got[k], ost[k]), f"{where}: env {e} field {k}"
+    import paper_2606_23348_amd as gen
     o = int(pool.obs_off[e])
     P, H, W = cfg.P, cfg.H, cfg.W
-    assert np.array_equal(obs_cpu[o:o + P * 8 * H * W].reshape(1, P, 8, H, W), oracle.observe(cfg, ost)), \
+    assert np.array_equal(gen.pool_env_obs(obs_cpu, o, H, W, P).reshape(1, P, 8, H, W), oracle.observe(cfg, ost)), \
         f"{where}: env {e} obs"
+    PS = gen.plane_stride(H, W)
+    assert not obs_cpu[o:o + P * 8 * PS].reshape(P * 8, PS)[:, H * W:].any(), f"{where}: env {e} plane padding"
     if next_act is not None:
         sl = pool.env_slice(e)
         assert np.array_equal(act_cpu[sl], next_act[0]), f"{where}: env {e} actions"
@@ -99,10 +102,12 @@ def test_pool_trajectory_parity(gen, lo, hi, n, steps):
                           oracle.sample(cfgs[e], osts[e], actor, t + 1))
 
 
-def _digest(gen, specs, tuning, steps=25):
+def _digest(gen, specs, tuning, steps=25, buckets=None):
     import torch
     pool = gen.Pool(specs, common_params(gen), seed=9)
     pool.set_tuning(**tuning)
+    if buckets is not None:
+        pool.set_buckets(buckets(pool.buckets()))
     pool.reset(actor_seed=3)
     for _ in range(steps):
         pool.step(actor_seed=3)
@@ -116,6 +121,44 @@ def test_pool_results_independent_of_packing(gen):
     for tun in (dict(waves_per_group=2, grid=0, order=0), dict(waves_per_group=4, grid=0, order=1),
                 dict(waves_per_group=1, grid=37, order=1), dict(waves_per_group=2, grid=100, order=0)):
         assert _digest(gen, specs, tun) == ref, tun
+
+    # per-bucket packings: every bucket its own choice, one launch per distinct packing
+    def mixed(bks):
+        choices = [(1, 2), (2, 1), (4, 1), (1, 1)]
+        return [dict(n_players=b["n_players"], words=b["words"], waves_per_group=choices[i % 4][0],
+                     waves_per_env=choices[i % 4][1]) for i, b in enumerate(bks)]
+
+    def two_waves(bks):
+        return [dict(n_players=b["n_players"], words=b["words"], waves_per_group=1, waves_per_env=2) for b in bks]
+
+    assert _digest(gen, specs, dict(waves_per_group=1, grid=0, order=0), buckets=mixed) == ref
+    assert _digest(gen, specs, dict(waves_per_group=2, grid=0, order=1), buckets=two_waves) == ref
+    assert _digest(gen, specs, dict(waves_per_group=1, grid=64, order=0), buckets=mixed) == ref
+
+
+def test_pool_bucket_packing_parity(gen):
+    """Buckets with two waves per env (later players' planes on the second
+    wave) and others packed 2 per workgroup, against the oracle env by env."""
+    import torch
+    specs = random_specs(90, 21, 4, 20)
+    seed, actor = 19, 940
+    pool = gen.Pool(specs, common_params(gen), seed=seed)
+    bks = pool.buckets()
+    pool.set_buckets([dict(n_players=b["n_players"], words=b["words"], waves_per_group=1 if i % 2 == 0 else 2,
+                           waves_per_env=2 if i % 2 == 0 else 1) for i, b in enumerate(bks)])
+    pool.reset(actor_seed=actor)
+    cfgs = [env_cfg(specs, e, seed) for e in range(pool.n)]
+    osts = [oracle.reset(c, 1)[0] for c in cfgs]
+    for t in range(150):
+        pool.step(actor_seed=actor)
+        torch.cuda.synchronize()
+        obs, act = pool.obs.cpu().numpy(), pool.actions.cpu().numpy()
+        rew, done = pool.rewards.cpu().numpy(), pool.dones.cpu().numpy()
+        for e in range(pool.n):
+            r, d = oracle.step(cfgs[e], osts[e], oracle.sample(cfgs[e], osts[e], actor, t))
+            assert np.array_equal(rew[pool.env_slice(e)], r[0]) and done[e] == d[0], f"step {t} env {e}"
+            if t % 5 == 0 or t == 149:
+                check_env(pool, e, cfgs[e], osts[e], obs, act, f"step {t}", oracle.sample(cfgs[e], osts[e], actor, t + 1))
 
 
 def test_pool_graph_replay_equals_eager(gen):

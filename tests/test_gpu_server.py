@@ -39,14 +39,19 @@ def common(gen):
                            city_army_max=50, auto_reset=1)
 
 
+def gen_mod():
+    import paper_2606_23348_amd
+    return paper_2606_23348_amd
+
+
 def snapshot(srv, gid, specs):
     """Every env's state and the bytes the step defines (each env's
     observation block, not the alignment padding between blocks)."""
     b = srv.buffers(gid)
     st = [srv.get_env(gid, e, int(specs["H"][e]), int(specs["W"][e]), int(specs["P"][e])) for e in range(b["n_envs"])]
     obs = b["obs"].cpu().numpy()
-    blocks = np.concatenate([obs[int(b["obs_off"][e]):int(b["obs_off"][e]) + int(specs["P"][e]) * 8 *
-                                 int(specs["H"][e]) * int(specs["W"][e])] for e in range(b["n_envs"])])
+    blocks = np.concatenate([gen_mod().pool_env_obs(obs, int(b["obs_off"][e]), int(specs["H"][e]), int(specs["W"][e]),
+                                                    int(specs["P"][e])).reshape(-1) for e in range(b["n_envs"])])
     return st, blocks, b["actions"].cpu().numpy(), b["rewards"].cpu().numpy(), b["dones"].cpu().numpy()
 
 
