@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2606_23348_amd/csrc/kernels.hip", "paper_2606_23348_amd/csrc/features.hip",
                   "paper_2606_23348_amd/csrc/device.hpp", "paper_2606_23348_amd/csrc/internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-EXTRAS = ("step_alone", "features", "copy", "c3", "rollout", "served", "pool", "served_mix")
+EXTRAS = ("sustained", "step_alone", "features", "copy", "c3", "rollout", "served", "pool", "served_mix")
 
 
 _T0 = time.perf_counter()
@@ -263,7 +263,7 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
     buckets, bucket_report = [], {}
     if tune_it:
         buckets, bucket_report = tuner.tune_buckets(specs, common, seed=wl.seed, actor_seed=wl.actor_seed, base=best,
-                                                    steps=8, cache_path=None, progress=log)
+                                                    cache_path=None, progress=log)
 
     def timed(table) -> float:
         """Seconds per step of graph replays (K steps per graph) with the
@@ -469,7 +469,7 @@ def main() -> int:
     ap.add_argument("--cpu-envs", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--calib-copy", type=int, default=0,
-                    help="only run N copies of 1 GiB (counter calibration run) and exit")
+                    help="only run N streaming copies of 1 GiB (counter calibration run) and exit")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain workload only (no served, pooled or copy-ceiling legs)")
     ap.add_argument("--extras", default=",".join(EXTRAS),
@@ -492,7 +492,7 @@ def main() -> int:
         src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)
         for _ in range(args.calib_copy):
-            dst.copy_(src)
+            gen.gen_stream_copy(dst, src)          # k_stream_copy: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": n, "copies": args.calib_copy}))
         return 0
@@ -573,8 +573,22 @@ def main() -> int:
         print(f"unknown extra legs {sorted(unknown)}", file=sys.stderr)
         return 2
     log(f"headline {wl.name}: {value / 1e6:.1f} M frames/s")
+    if "sustained" in legs:
+        # the same launch, 2,000 more back to back right after the timed
+        # region: the rate a long run settles at (the first tens of launches
+        # of a fresh process run at a different rate on some boxes)
+        n_s = 2000
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record(stream)
+        for t in range(n_s):
+            b.step_sample(wl.actor_seed, W + K + n_lat + t + 1)
+        q1.record(stream)
+        torch.cuda.synchronize()
+        s_avg = q0.elapsed_time(q1) / 1e3 / n_s
+        out["sustained"] = {"launches": n_s, "step_kernel_ms_mean": s_avg * 1e3, "frames_per_s": E / s_avg,
+                            "roofline_frac": by["step"] * E / s_avg / 1e9 / HBM_PEAK_GBS}
     if "step_alone" in legs:
-        out["step_alone"] = run_step_alone(b, wl, torch, stream, min(K, 1000), W + K + 1)
+        out["step_alone"] = run_step_alone(b, wl, torch, stream, min(K, 1000), W + K + n_lat + 2001)
     if "features" in legs:
         log("features leg")
         out["features"] = run_features(b, wl, torch, stream, 100, W + K + min(K, 1000) + 1)

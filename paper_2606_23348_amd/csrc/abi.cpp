@@ -242,7 +242,8 @@ void pool_make_order(gen_pool &pl)
     }
 }
 
-// One step of every env: one launch per segment of the work list.
+// One step of every env: one launch per segment of the work list, in order
+// on the caller's stream.
 hipError_t pool_step_launches(const gen_pool &pl, gen::PoolArgs a, bool act, hipStream_t s)
 {
     for (const auto &sg : pl.segments) {

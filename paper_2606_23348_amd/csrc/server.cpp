@@ -150,19 +150,32 @@ struct Group {
     int waiters = 0;            // clients blocked on cv (close waits for them to leave)
     std::condition_variable cv; // completion of this group's tickets
     std::atomic<uint64_t> completed{0};   // requests finished (lock-free progress check)
+    gen::ServeReq req{};        // its request record (filled once its buffers are carved)
 };
 
+// A ticket lives in a ring slot (id & mask) until it is collected or
+// 2^18 newer tickets have been issued; a pending ticket is never
+// overwritten.  Its group pointer is valid while the ticket is pending:
+// a group is closed only after its queued tickets were failed and its work
+// in flight finished.
 struct Ticket {
-    uint64_t group;
-    int64_t t_submit;
-    int status;                 // 1 pending, 0 done, <0 failed
+    uint64_t id = 0;            // 0: free slot
+    Group *g = nullptr;
+    int64_t t_submit = 0;
+    int status = 0;             // 1 pending, 0 done, <0 failed
+};
+constexpr uint64_t kTicketRing = 1ull << 18;
+
+struct QEntry {                 // a queued request
+    uint64_t ticket;
+    Group *g;                   // valid while the ticket is pending
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    std::vector<std::pair<uint64_t, uint64_t>> reqs;   // (ticket, group)
+    std::vector<std::pair<uint64_t, Group *>> reqs;    // (ticket, group) of the launch
     gen::ServeReq *h_table = nullptr;                  // pinned
     uint64_t d_table_off = 0;                          // in the arena
     uint64_t envs = 0;
@@ -184,8 +197,8 @@ struct gen_server {
     std::mutex mu;
     std::condition_variable cv_sched;
     std::unordered_map<uint64_t, std::unique_ptr<Group>> groups;
-    std::unordered_map<uint64_t, Ticket> tickets;
-    std::deque<uint64_t> queue;                        // pending tickets, arrival order
+    std::vector<Ticket> ring = std::vector<Ticket>(kTicketRing);   // tickets by id & (kTicketRing - 1)
+    std::deque<QEntry> queue;                          // pending requests, arrival order
     std::vector<Slot> slots;
     uint64_t next_group = 1, next_ticket = 1;
     std::thread sched;
@@ -205,25 +218,52 @@ namespace {
 
 int sfail(int code, const std::string &msg) { return gen::set_error(code, msg.c_str()); }
 
+Ticket *ticket_of(gen_server &s, uint64_t tk)
+{
+    Ticket &t = s.ring[tk & (kTicketRing - 1)];
+    return (tk != 0 && t.id == tk) ? &t : nullptr;
+}
+
+// A new pending ticket of group g (lock held); 0 if its ring slot still
+// holds a pending ticket 2^18 tickets older.
+uint64_t new_ticket(gen_server &s, Group *g)
+{
+    const uint64_t tk = s.next_ticket;
+    Ticket &t = s.ring[tk & (kTicketRing - 1)];
+    if (t.id != 0 && t.status == 1) return 0;
+    s.next_ticket += 1;
+    t.id = tk;
+    t.g = g;
+    t.t_submit = now_ns();
+    t.status = 1;
+    return tk;
+}
+
+// Fail every queued request of group g with `status` (lock held).
+void fail_queued(gen_server &s, const Group *g, int status)
+{
+    for (const QEntry &q : s.queue) {
+        Ticket *t = ticket_of(s, q.ticket);
+        if (t != nullptr && t->status == 1 && q.g == g) t->status = status;
+    }
+}
+
 void complete_slot(gen_server &s, Slot &sl, int status)
 {
     const int64_t t = now_ns();
-    for (auto &[tk, gid] : sl.reqs) {
-        auto it = s.tickets.find(tk);
-        if (it != s.tickets.end()) {
-            it->second.status = status;
-            if (status == 0) s.lat.add(t - it->second.t_submit);
+    for (auto &[tk, g] : sl.reqs) {
+        Ticket *tp = ticket_of(s, tk);
+        if (tp != nullptr) {
+            tp->status = status;
+            if (status == 0) s.lat.add(t - tp->t_submit);
         }
-        auto g = s.groups.find(gid);
-        if (g != s.groups.end()) {
-            g->second->busy = false;
-            if (status == 0) {
-                s.st_requests += 1;
-                s.st_frames += (uint64_t)g->second->n_envs;
-            }
-            g->second->completed.fetch_add(1, std::memory_order_release);
-            g->second->cv.notify_all();
+        g->busy = false;                 // a group in a launch is never closed before it finishes
+        if (status == 0) {
+            s.st_requests += 1;
+            s.st_frames += (uint64_t)g->n_envs;
         }
+        g->completed.fetch_add(1, std::memory_order_release);
+        if (g->waiters > 0 || g->closing) g->cv.notify_all();   // a waiting client or close
     }
     sl.reqs.clear();
     sl.busy = false;
@@ -269,6 +309,7 @@ bool carve(gen_server &s, Group &g)
     g.off_act = o[2];
     g.off_rew = o[3];
     g.off_done = o[4];
+    fill_req(s, g, &g.req);
     return true;
 }
 
@@ -333,8 +374,7 @@ void admit_pending(gen_server &s)
         } else {
             g->failed = true;
             uncarve(s, *g);
-            for (auto &[tk, t] : s.tickets)
-                if (t.group == g->id && t.status == 1) t.status = GEN_EHIP;
+            fail_queued(s, g, GEN_EHIP);
         }
         g->cv.notify_all();
     }
@@ -379,8 +419,8 @@ void scheduler(gen_server *sp)
                 // shutting down: leave once nothing more can be launched
                 std::lock_guard<std::mutex> g(s.mu);
                 for (auto it = s.queue.begin(); it != s.queue.end();) {
-                    auto t = s.tickets.find(*it);
-                    if (t == s.tickets.end() || t->second.status != 1) {
+                    const Ticket *t = ticket_of(s, it->ticket);
+                    if (t == nullptr || t->status != 1) {
                         it = s.queue.erase(it);
                         s.n_queued.fetch_sub(1, std::memory_order_release);
                     } else {
@@ -423,13 +463,11 @@ void scheduler(gen_server *sp)
             // max_wait_us.  Closed-loop clients then settle into cohorts that
             // alternate between the GPU and the queue.
             int64_t ready = 0, oldest = INT64_MAX, inflight = 0;
-            for (uint64_t tk : s.queue) {
-                auto t = s.tickets.find(tk);
-                if (t == s.tickets.end() || t->second.status != 1) continue;
-                auto gi = s.groups.find(t->second.group);
-                if (gi == s.groups.end() || gi->second->busy) continue;
-                ready += gi->second->n_envs;
-                oldest = std::min(oldest, t->second.t_submit);
+            for (const QEntry &q : s.queue) {
+                const Ticket *t = ticket_of(s, q.ticket);
+                if (t == nullptr || t->status != 1 || q.g->busy) continue;
+                ready += q.g->n_envs;
+                oldest = std::min(oldest, t->t_submit);
             }
             for (const auto &x : s.slots)
                 if (x.busy) inflight += (int64_t)x.envs;
@@ -444,24 +482,23 @@ void scheduler(gen_server *sp)
             Slot &sl = *free_slot;
             uint32_t wg = 0, lds = 0, max_envs = 0;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
-                auto tk = s.tickets.find(*it);
-                if (tk == s.tickets.end() || tk->second.status != 1) {
+                Ticket *tk = ticket_of(s, it->ticket);
+                if (tk == nullptr || tk->status != 1) {
                     it = s.queue.erase(it);
                     s.n_queued.fetch_sub(1, std::memory_order_release);
                     continue;
                 }
-                auto gi = s.groups.find(tk->second.group);
-                if (gi == s.groups.end() || gi->second->closing) {
-                    tk->second.status = GEN_ENOTFOUND;
+                Group &g = *it->g;
+                if (g.closing) {
+                    tk->status = GEN_ENOTFOUND;
                     it = s.queue.erase(it);
                     s.n_queued.fetch_sub(1, std::memory_order_release);
                     continue;
                 }
-                Group &g = *gi->second;
                 if (g.busy || (s.max_batch_envs && n_req > 0 && wg + (uint32_t)g.n_envs > s.max_batch_envs)) { ++it; continue; }
                 g.busy = true;
-                fill_req(s, g, &sl.h_table[n_req]);
-                sl.reqs.emplace_back(*it, g.id);
+                sl.h_table[n_req] = g.req;
+                sl.reqs.emplace_back(it->ticket, &g);
                 wg += (uint32_t)g.n_envs;
                 max_envs = std::max(max_envs, (uint32_t)g.n_envs);
                 lds = std::max(lds, g.pool->lds_per_wave);
@@ -538,8 +575,7 @@ int gen_server_destroy(gen_server *s)
         for (uint64_t id : s->pending) {
             auto it = s->groups.find(id);
             if (it == s->groups.end()) continue;
-            for (auto &[tk, t] : s->tickets)
-                if (t.group == id && t.status == 1) t.status = GEN_ENOTFOUND;
+            fail_queued(*s, it->second.get(), GEN_ENOTFOUND);
             it->second->cv.notify_all();
         }
         s->pending.clear();
@@ -670,9 +706,9 @@ int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
         auto it = s->groups.find(group);
         if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
         if (it->second->failed) return sfail(GEN_EHIP, "admission of the group failed");
-        const uint64_t tk = s->next_ticket++;
-        s->tickets[tk] = Ticket{group, now_ns(), 1};
-        s->queue.push_back(tk);
+        const uint64_t tk = new_ticket(*s, it->second.get());
+        if (tk == 0) return sfail(GEN_EBUSY, "too many requests pending");
+        s->queue.push_back({tk, it->second.get()});
         s->n_queued.fetch_add(1, std::memory_order_release);
         s->n_submitted.fetch_add(1, std::memory_order_release);
         *ticket = tk;
@@ -685,19 +721,18 @@ int gen_server_wait(gen_server *s, uint64_t ticket, int64_t timeout_us)
 {
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return sfail(GEN_ENOTFOUND, "unknown ticket");
-    auto gi = s->groups.find(it->second.group);
-    if (it->second.status == 1 && gi != s->groups.end()) {
-        Group &g = *gi->second;            // stays alive while waiters > 0 (close waits)
+    Ticket *t = ticket_of(*s, ticket);
+    if (t == nullptr) return sfail(GEN_ENOTFOUND, "unknown ticket");
+    if (t->status == 1) {
+        Group &g = *t->g;                  // a pending ticket's group is open; close waits for waiters
         const auto deadline = Clock::now() + std::chrono::microseconds(timeout_us < 0 ? 0 : timeout_us);
         g.waiters += 1;
         bool timed_out = false;
-        while (it->second.status == 1) {
+        while (t->status == 1) {           // a pending ticket's slot is never reused
             if (timeout_us < 0) {
                 g.cv.wait(lk);
             } else if (g.cv.wait_until(lk, deadline) == std::cv_status::timeout) {
-                timed_out = it->second.status == 1;
+                timed_out = t->status == 1;
                 break;
             }
         }
@@ -705,9 +740,8 @@ int gen_server_wait(gen_server *s, uint64_t ticket, int64_t timeout_us)
         if (g.closing) g.cv.notify_all();
         if (timed_out) return GEN_EBUSY;
     }
-    const int st = it->second.status;
-    s->tickets.erase(it);
-    if (st == 1) return sfail(GEN_ENOTFOUND, "group closed");
+    const int st = t->status;
+    t->id = 0;                             // collected
     if (st != 0) return sfail(st, s->error.empty() ? "request failed" : s->error);
     return GEN_OK;
 }
@@ -721,11 +755,7 @@ int gen_server_close(gen_server *s, uint64_t group)
         if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
         Group &g = *it->second;
         g.closing = true;
-        for (auto &[tk, t] : s->tickets)
-            if (t.group == group && t.status == 1) {
-                const bool queued = std::find(s->queue.begin(), s->queue.end(), tk) != s->queue.end();
-                if (queued) t.status = GEN_ENOTFOUND;
-            }
+        fail_queued(*s, &g, GEN_ENOTFOUND);
         g.cv.notify_all();
         if (g.phase == Group::PENDING) {
             // never admitted: it holds no memory
@@ -907,18 +937,17 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
                 for (Cl *x : ready) {
                     ClientGroup &grp = cg[(size_t)x->c][(size_t)x->gi];
                     if (grp.outstanding) {
-                        auto it = s->tickets.find(grp.ticket);
-                        if (it == s->tickets.end() || it->second.status != 0) { failure = GEN_EHIP; break; }
-                        s->tickets.erase(it);
+                        Ticket *t = ticket_of(*s, grp.ticket);
+                        if (t == nullptr || t->status != 0) { failure = GEN_EHIP; break; }
+                        t->id = 0;                  // collected
                         grp.outstanding = false;
                         grp.steps += 1;
                     }
-                    auto gi = s->groups.find(grp.id);
-                    if (gi == s->groups.end() || gi->second->closing) { failure = GEN_ENOTFOUND; break; }
+                    if (grp.g->closing) { failure = GEN_ENOTFOUND; break; }
                     grp.mark = grp.g->completed.load(std::memory_order_acquire);
-                    const uint64_t tk = s->next_ticket++;
-                    s->tickets[tk] = Ticket{grp.id, now_ns(), 1};
-                    s->queue.push_back(tk);
+                    const uint64_t tk = new_ticket(*s, grp.g);
+                    if (tk == 0) { failure = GEN_EBUSY; break; }
+                    s->queue.push_back({tk, grp.g});
                     s->n_queued.fetch_add(1, std::memory_order_release);
                     s->n_submitted.fetch_add(1, std::memory_order_release);
                     grp.ticket = tk;

@@ -11,8 +11,8 @@ cached per (GPU architecture, pool signature) in a JSON file.
     pool.set_tuning(**best)
 
 tune_buckets() then chooses a packing per size bucket (players, 64-cell
-words): envs per workgroup and one or two waves per env, timed bucket by
-bucket, verified on the whole pool the same way:
+words): envs per workgroup and one or two waves per env, each bucket's
+choice timed on the whole pool, verified the same way:
 
     buckets, report = tune_buckets(specs, common, seed=4, actor_seed=1004, base=best)
     pool.set_buckets(buckets)
@@ -129,17 +129,20 @@ def _time_steps(pool: Pool, actor_seed: int, steps: int, warmup: int, stream) ->
 
 
 def tune_buckets(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, base: dict | None = None,
-                 steps: int = 10, warmup: int = 3, verify_steps: int = 3, min_envs: int = 2048,
-                 cache_path: str | None = DEFAULT_CACHE, force: bool = False, progress=None):
-    """Per-bucket packing: each size bucket (players, 64-cell words) of the
-    pool with at least min_envs envs is timed on its own, as a pool of just
-    its envs, under every candidate of BUCKET_CANDIDATES (envs per
-    workgroup, one or two waves per env); the fastest is kept for it, the
-    other buckets keep the pool-wide packing `base`.  The table is accepted
-    only if the whole pool, from the same reset, gives bit-identical results
-    under it and under `base`.  Returns (table, report) where report holds
-    every candidate's time per bucket.  Cached per (architecture, pool
-    signature)."""
+                 steps: int = 20, warmup: int = 3, verify_steps: int = 3, min_envs: int = 2048,
+                 min_gain: float = 0.005, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+                 progress=None):
+    """Per-bucket packing, chosen greedily on the whole pool: starting from
+    the pool-wide packing `base`, the buckets (players, 64-cell words) with
+    at least min_envs envs are visited largest first, and each keeps the
+    candidate of BUCKET_CANDIDATES (envs per workgroup, one or two waves per
+    env) that makes a step of the whole pool fastest, if it beats the
+    current table by more than min_gain (a bucket whose packing differs from
+    the others' takes a launch of its own, so the whole pool is what is
+    timed).  The table is accepted only if the pool, from the same reset,
+    gives bit-identical results under it and under `base`.  Returns (table,
+    report) where report holds every trial's step time.  Cached per
+    (architecture, pool signature, base)."""
     import torch
     base = dict(base or {"waves_per_group": 1, "grid": 0, "order": 0})
     arch = torch.cuda.get_device_properties(0).gcnArchName
@@ -152,34 +155,40 @@ def tune_buckets(specs: dict, common=None, seed: int = 0, actor_seed: int = 1, b
     stream = torch.cuda.current_stream()
     full = Pool(specs, common, seed=seed)
     full.set_tuning(**base, stream=stream)
-    buckets = full.buckets()
-    P = np.asarray(specs["P"], np.int64)
-    words = (np.asarray(specs["H"], np.int64) * np.asarray(specs["W"], np.int64) + 63) // 64
-    table, report = [], {}
-    for b in buckets:
+    full.reset(actor_seed=actor_seed, stream=stream)
+
+    def step_us(table):
+        full.set_buckets(table, stream=stream)
+        return _time_steps(full, actor_seed, steps, warmup, stream)
+
+    table = []
+    cur = step_us(table)
+    report = {"base": cur}
+    default = {"waves_per_group": int(base["waves_per_group"]), "waves_per_env": 1}
+    for b in sorted(full.buckets(), key=lambda x: -x["n_envs"]):
         if b["n_envs"] < min_envs:
             continue
-        idx = np.flatnonzero((P == b["n_players"]) & (words == b["words"]))
-        sub = Pool({k: np.asarray(specs[k])[idx] for k in SPEC_FIELDS}, common, seed=seed)
-        sub.set_tuning(**base, stream=stream)
-        times = {}
-        for c in BUCKET_CANDIDATES:
-            entry = dict(n_players=b["n_players"], words=b["words"], **c)
-            try:
-                sub.set_buckets([entry], stream=stream)
-            except GenError:
-                times[json.dumps(c, sort_keys=True)] = None      # does not fit (LDS)
-                continue
-            sub.reset(actor_seed=actor_seed, stream=stream)
-            times[json.dumps(c, sort_keys=True)] = _time_steps(sub, actor_seed, steps, warmup, stream)
         name = f"P{b['n_players']}-w{b['words']}"
-        report[name] = {"n_envs": b["n_envs"], "us": times}
-        best = min((k for k in times if times[k] is not None), key=times.get)
-        table.append(dict(n_players=b["n_players"], words=b["words"], **json.loads(best)))
+        best, best_us = None, cur
+        for c in BUCKET_CANDIDATES:
+            if c == default:
+                continue
+            trial = table + [dict(n_players=b["n_players"], words=b["words"], **c)]
+            try:
+                us = step_us(trial)
+            except GenError:
+                us = None                               # does not fit (LDS)
+            report[f"{name} {json.dumps(c, sort_keys=True)}"] = us
+            if us is not None and us < best_us * (1.0 - min_gain):
+                best, best_us = trial, us
+        if best is not None:
+            table, cur = best, best_us
         if progress is not None:
-            progress(f"tune bucket {name} ({b['n_envs']} envs): best {best} {times[best]:.1f} us")
-        del sub
+            progress(f"tune bucket {name} ({b['n_envs']} envs): {'kept ' + json.dumps(table[-1]) if best else 'pool-wide'}"
+                     f", step {cur:.1f} us")
+    report["table"] = cur
     # the table must not change any result
+    full.set_buckets([], stream=stream)
     _run_from_reset(full, actor_seed, verify_steps, stream)
     ref = full.digest()
     full.set_buckets(table, stream=stream)
