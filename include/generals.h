@@ -432,12 +432,16 @@ typedef struct gen_server_stats {
 
 /* d_arena: device buffer of arena_bytes (256-byte aligned) the server may
  * use; n_launch_streams: launches in flight (1..4); max_batch_envs: cap on
- * envs per launch (0 = no cap).  Starts the scheduler thread. */
+ * envs per launch (0 = no cap).  Starts the scheduler thread.  The server
+ * keeps one record per open group in a table carved from the arena at
+ * creation (16,384 records of 152 bytes); a launch carries at most 1,024
+ * requests, the list itself passed as the kernel argument (no copy). */
 int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_streams, int32_t max_batch_envs,
                       gen_server **out);
 /* Finishes the work in flight, stops the scheduler, releases host objects. */
 int gen_server_destroy(gen_server *srv);
-/* Open a group: plan it, and if its buffers fit in the arena now (and no
+/* Open a group: plan it (GEN_EBUSY when 16,384 groups are open or queued
+ * already), and if its buffers fit in the arena now (and no
  * earlier group is waiting), carve them and generate its maps (blocking):
  * GEN_OK, *group is steppable.  If they do not fit, the group is queued:
  * GEN_EBUDGET with *group set, and it is admitted (buffers carved, maps

@@ -35,6 +35,33 @@ using Clock = std::chrono::steady_clock;
 
 int64_t now_ns() { return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count(); }
 
+// Test-and-test-and-set lock for the server state.  Its critical sections
+// last microseconds and are taken by the scheduler once per launch and by
+// every client thread once per batch of submissions; with a sleeping mutex
+// each contended hand-over costs the waiter a futex wake-up of tens of
+// microseconds, which the scheduler paid on every launch.  A waiter spins
+// (with the pause hint), then yields its core.
+class SpinLock {
+public:
+    void lock()
+    {
+        for (int spins = 0;;) {
+            if (!held_.exchange(true, std::memory_order_acquire)) return;
+            while (held_.load(std::memory_order_relaxed)) {
+                if (++spins < 2048) __builtin_ia32_pause();
+                else std::this_thread::yield();
+            }
+        }
+    }
+    bool try_lock() { return !held_.load(std::memory_order_relaxed) && !held_.exchange(true, std::memory_order_acquire); }
+    void unlock() { held_.store(false, std::memory_order_release); }
+
+private:
+    std::atomic<bool> held_{false};
+};
+using Lock = std::unique_lock<SpinLock>;
+using Guard = std::lock_guard<SpinLock>;
+
 // First-fit allocator over [0, size) of the arena, 256-byte granules.
 class Arena {
   public:
@@ -148,9 +175,12 @@ struct Group {
     bool closing = false;
     bool failed = false;        // its admission failed (map generation); its tickets fail
     int waiters = 0;            // clients blocked on cv (close waits for them to leave)
-    std::condition_variable cv; // completion of this group's tickets
-    std::atomic<uint64_t> completed{0};   // requests finished (lock-free progress check)
-    gen::ServeReq req{};        // its request record (filled once its buffers are carved)
+    std::condition_variable_any cv; // completion of this group's tickets
+    // requests finished (lock-free progress check), on a cache line of its
+    // own: client threads poll it while the scheduler updates the fields above
+    alignas(64) std::atomic<uint64_t> completed{0};
+    alignas(64) gen::ServeReq req{};   // its request record (filled once its buffers are carved)
+    uint32_t tidx = 0;                 // its record's index in the device table of group records
 };
 
 // A ticket lives in a ring slot (id & mask) until it is collected or
@@ -176,8 +206,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<std::pair<uint64_t, Group *>> reqs;    // (ticket, group) of the launch
-    gen::ServeReq *h_table = nullptr;                  // pinned
-    uint64_t d_table_off = 0;                          // in the arena
+    gen::ServeLaunch la{};                             // the launch's kernel argument
     uint64_t envs = 0;
 };
 
@@ -194,12 +223,15 @@ struct gen_server {
     int64_t max_wait_us = 100;
     int64_t open_envs = 0;                             // envs of the open groups
     Arena alloc;
-    std::mutex mu;
-    std::condition_variable cv_sched;
+    SpinLock mu;
+    std::condition_variable_any cv_sched;
+    std::atomic<bool> sched_idle{false};              // the scheduler sleeps on cv_sched
     std::unordered_map<uint64_t, std::unique_ptr<Group>> groups;
     std::vector<Ticket> ring = std::vector<Ticket>(kTicketRing);   // tickets by id & (kTicketRing - 1)
     std::deque<QEntry> queue;                          // pending requests, arrival order
     std::vector<Slot> slots;
+    uint64_t d_groups_off = 0;                         // device table of group records (in the arena)
+    std::vector<uint32_t> free_tidx;                   // its free entries
     uint64_t next_group = 1, next_ticket = 1;
     std::thread sched;
     std::atomic<bool> stop{false};
@@ -334,7 +366,11 @@ int make_maps(gen_server &s, Group &g)
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     int rc = GEN_OK;
     if (e == hipSuccess) {
-        rc = gen_pool_reset(g.pool, s.arena + g.off_state, g.sz_state, s.arena + g.off_obs,
+        // the group's record in the device table, read by every launch of its requests
+        e = hipMemcpyAsync(reinterpret_cast<gen::ServeReq *>(s.arena + s.d_groups_off) + g.tidx, &g.req,
+                           sizeof(gen::ServeReq), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            rc = gen_pool_reset(g.pool, s.arena + g.off_state, g.sz_state, s.arena + g.off_obs,
                             g.actor ? reinterpret_cast<int32_t *>(s.arena + g.off_act) : nullptr, g.actor_seed, st);
         if (rc == GEN_OK) e = hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
@@ -350,7 +386,7 @@ void admit_pending(gen_server &s)
 {
     std::vector<Group *> todo;
     {
-        std::lock_guard<std::mutex> lk(s.mu);
+        Guard lk(s.mu);
         while (!s.pending.empty()) {
             auto it = s.groups.find(s.pending.front());
             if (it == s.groups.end() || it->second->phase != Group::PENDING) {
@@ -366,7 +402,7 @@ void admit_pending(gen_server &s)
     }
     for (Group *g : todo) {
         const int rc = make_maps(s, *g);
-        std::lock_guard<std::mutex> lk(s.mu);
+        Guard lk(s.mu);
         g->phase = Group::OPEN;
         g->busy = false;
         if (rc == GEN_OK) {
@@ -417,7 +453,7 @@ void scheduler(gen_server *sp)
         if (!any_done && !try_launch) {
             if (stopping && n_busy == 0) {
                 // shutting down: leave once nothing more can be launched
-                std::lock_guard<std::mutex> g(s.mu);
+                Guard g(s.mu);
                 for (auto it = s.queue.begin(); it != s.queue.end();) {
                     const Ticket *t = ticket_of(s, it->ticket);
                     if (t == nullptr || t->status != 1) {
@@ -434,13 +470,15 @@ void scheduler(gen_server *sp)
                 // of microseconds, which every request's latency would pay)
                 std::this_thread::yield();
             } else {
-                std::unique_lock<std::mutex> lk(s.mu);
+                Lock lk(s.mu);
+                s.sched_idle.store(true, std::memory_order_release);
                 s.cv_sched.wait_for(lk, std::chrono::milliseconds(5),
                                     [&] { return s.n_queued.load() > 0 || s.stop.load(); });
+                s.sched_idle.store(false, std::memory_order_release);
             }
             continue;
         }
-        std::unique_lock<std::mutex> lk(s.mu);
+        Lock lk(s.mu);
         for (size_t i = 0; i < ns; ++i) {
             if (!done[i]) continue;
             if (qs[i] == hipSuccess) {
@@ -497,7 +535,7 @@ void scheduler(gen_server *sp)
                 }
                 if (g.busy || (s.max_batch_envs && n_req > 0 && wg + (uint32_t)g.n_envs > s.max_batch_envs)) { ++it; continue; }
                 g.busy = true;
-                sl.h_table[n_req] = g.req;
+                sl.la.idx[n_req] = (uint16_t)g.tidx;
                 sl.reqs.emplace_back(it->ticket, &g);
                 wg += (uint32_t)g.n_envs;
                 max_envs = std::max(max_envs, (uint32_t)g.n_envs);
@@ -511,11 +549,9 @@ void scheduler(gen_server *sp)
                 sl.envs = wg;
                 s.st_launches += 1;
                 s.st_launch_envs += wg;
-                gen::ServeReq *d_table = reinterpret_cast<gen::ServeReq *>(s.arena + sl.d_table_off);
+                sl.la.n_req = n_req;
                 lk.unlock();
-                hipError_t e = hipMemcpyAsync(d_table, sl.h_table, n_req * sizeof(gen::ServeReq),
-                                              hipMemcpyHostToDevice, sl.stream);
-                if (e == hipSuccess) e = gen::launch_serve(s.arena, d_table, n_req, max_envs, lds, sl.stream);
+                hipError_t e = gen::launch_serve(sl.la, max_envs, lds, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
                 if (e != hipSuccess) {
                     lk.lock();
@@ -544,20 +580,23 @@ int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_stre
     s->arena = static_cast<uint8_t *>(d_arena);
     s->arena_bytes = arena_bytes;
     s->max_batch_envs = (uint32_t)max_batch_envs;
-    s->max_reqs = 8192;
+    s->max_reqs = gen::kServeMaxReqs;
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, d_arena) != hipSuccess) return sfail(GEN_EINVAL, "arena is not device memory");
     s->device = attr.device;
     (void)hipSetDevice(s->device);
     s->alloc.init(arena_bytes);
-    const uint64_t table_bytes = (uint64_t)s->max_reqs * sizeof(gen::ServeReq);
+    const uint64_t table_bytes = (uint64_t)gen::kServeMaxGroups * sizeof(gen::ServeReq);
+    if (!s->alloc.alloc(table_bytes, &s->d_groups_off)) return sfail(GEN_EBUDGET, "arena too small for the group table");
+    s->free_tidx.resize(gen::kServeMaxGroups);
+    for (uint32_t i = 0; i < gen::kServeMaxGroups; ++i) s->free_tidx[i] = gen::kServeMaxGroups - 1 - i;
     s->slots.resize((size_t)n_launch_streams);
     for (auto &sl : s->slots) {
-        if (!s->alloc.alloc(table_bytes, &sl.d_table_off)) return sfail(GEN_EBUDGET, "arena too small for the request tables");
+        sl.la.arena = s->arena;
+        sl.la.groups = reinterpret_cast<const gen::ServeReq *>(s->arena + s->d_groups_off);
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.h_table), table_bytes, hipHostMallocDefault) != hipSuccess)
-            return sfail(GEN_EHIP, "stream, event or pinned table allocation failed");
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+            return sfail(GEN_EHIP, "stream or event creation failed");
     }
     s->capacity = arena_bytes - s->alloc.used();
     s->sched = std::thread(scheduler, s.get());
@@ -569,7 +608,7 @@ int gen_server_destroy(gen_server *s)
 {
     if (s == nullptr) return GEN_OK;
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        Guard lk(s->mu);
         // groups still waiting for memory will not be admitted: their
         // requests fail, so the scheduler can drain the rest and stop
         for (uint64_t id : s->pending) {
@@ -587,7 +626,6 @@ int gen_server_destroy(gen_server *s)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.h_table) (void)hipHostFree(sl.h_table);
     }
     for (auto &[id, g] : s->groups) gen_pool_destroy(g->pool);
     delete s;
@@ -613,12 +651,18 @@ int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_e
     g->busy = true;              // not steppable until its maps exist
     Group *gp = g.get();
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        Guard lk(s->mu);
         if (group_bytes(*gp) > s->capacity) {
             gen_pool_destroy(pool);
             return sfail(GEN_EINVAL, "group of " + std::to_string(n_envs) + " envs needs " +
                                          std::to_string(group_bytes(*gp)) + " bytes, more than the arena holds");
         }
+        if (s->free_tidx.empty()) {
+            gen_pool_destroy(pool);
+            return sfail(GEN_EBUSY, std::to_string(gen::kServeMaxGroups) + " groups are open already");
+        }
+        gp->tidx = s->free_tidx.back();
+        s->free_tidx.pop_back();
         gp->id = s->next_group++;
         *group = gp->id;
         const bool now = s->pending.empty() && carve(*s, *gp);
@@ -633,11 +677,12 @@ int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_e
         }
     }
     rc = make_maps(*s, *gp);
-    std::lock_guard<std::mutex> lk(s->mu);
+    Guard lk(s->mu);
     if (rc != GEN_OK) {
         const std::string why = gen_last_error();
         uncarve(*s, *gp);
         gen_pool_destroy(gp->pool);
+        s->free_tidx.push_back(gp->tidx);
         s->groups.erase(gp->id);        // its id was never returned with GEN_OK, so no one holds tickets
         return sfail(rc, why);
     }
@@ -650,7 +695,7 @@ int gen_server_open(gen_server *s, uint64_t seed, uint64_t env_base, int32_t n_e
 int gen_server_wait_admitted(gen_server *s, uint64_t group, int64_t timeout_us)
 {
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
-    std::unique_lock<std::mutex> lk(s->mu);
+    Lock lk(s->mu);
     auto it = s->groups.find(group);
     if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
     Group &g = *it->second;
@@ -678,7 +723,7 @@ int gen_server_wait_admitted(gen_server *s, uint64_t group, int64_t timeout_us)
 int gen_server_buffers(gen_server *s, uint64_t group, gen_group_buffers *out)
 {
     if (s == nullptr || out == nullptr) return sfail(GEN_EINVAL, "server and out are required");
-    std::lock_guard<std::mutex> lk(s->mu);
+    Guard lk(s->mu);
     auto it = s->groups.find(group);
     if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
     const Group &g = *it->second;
@@ -701,7 +746,7 @@ int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
 {
     if (s == nullptr || ticket == nullptr) return sfail(GEN_EINVAL, "server and ticket are required");
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        Guard lk(s->mu);
         if (!s->error.empty()) return sfail(GEN_EHIP, s->error);
         auto it = s->groups.find(group);
         if (it == s->groups.end() || it->second->closing) return sfail(GEN_ENOTFOUND, "unknown group");
@@ -713,14 +758,14 @@ int gen_server_submit(gen_server *s, uint64_t group, uint64_t *ticket)
         s->n_submitted.fetch_add(1, std::memory_order_release);
         *ticket = tk;
     }
-    s->cv_sched.notify_one();
+    if (s->sched_idle.load(std::memory_order_acquire)) s->cv_sched.notify_one();
     return GEN_OK;
 }
 
 int gen_server_wait(gen_server *s, uint64_t ticket, int64_t timeout_us)
 {
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
-    std::unique_lock<std::mutex> lk(s->mu);
+    Lock lk(s->mu);
     Ticket *t = ticket_of(*s, ticket);
     if (t == nullptr) return sfail(GEN_ENOTFOUND, "unknown ticket");
     if (t->status == 1) {
@@ -750,7 +795,7 @@ int gen_server_close(gen_server *s, uint64_t group)
 {
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
     {
-        std::unique_lock<std::mutex> lk(s->mu);
+        Lock lk(s->mu);
         auto it = s->groups.find(group);
         if (it == s->groups.end()) return sfail(GEN_ENOTFOUND, "unknown group");
         Group &g = *it->second;
@@ -770,6 +815,7 @@ int gen_server_close(gen_server *s, uint64_t group)
             }
         }
         gen_pool_destroy(g.pool);
+        s->free_tidx.push_back(g.tidx);
         s->groups.erase(it);
     }
     admit_pending(*s);
@@ -781,7 +827,7 @@ int gen_server_set_batching(gen_server *s, int64_t min_batch_envs, int64_t max_w
     if (s == nullptr) return sfail(GEN_EINVAL, "server is NULL");
     if (min_batch_envs < 0 || max_wait_us < 0) return sfail(GEN_EINVAL, "min_batch_envs and max_wait_us must be >= 0");
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        Guard lk(s->mu);
         s->min_batch_envs = min_batch_envs;
         s->max_wait_us = max_wait_us;
     }
@@ -792,7 +838,7 @@ int gen_server_set_batching(gen_server *s, int64_t min_batch_envs, int64_t max_w
 int gen_server_report(gen_server *s, gen_server_stats *out, int32_t reset)
 {
     if (s == nullptr || out == nullptr) return sfail(GEN_EINVAL, "server and out are required");
-    std::lock_guard<std::mutex> lk(s->mu);
+    Guard lk(s->mu);
     std::memset(out, 0, sizeof *out);
     out->requests = s->st_requests;
     out->frames = s->st_frames;
@@ -835,7 +881,7 @@ struct ClientGroup {
 
 Group *group_of(gen_server *s, uint64_t id)
 {
-    std::lock_guard<std::mutex> lk(s->mu);
+    Guard lk(s->mu);
     auto it = s->groups.find(id);
     return it == s->groups.end() ? nullptr : it->second.get();
 }
@@ -932,7 +978,7 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
             // 3. collect the finished tickets and submit the next requests
             // under one lock acquisition for the whole batch
             {
-                std::lock_guard<std::mutex> lk(s->mu);
+                Guard lk(s->mu);
                 if (!s->error.empty()) { failure = GEN_EHIP; break; }
                 for (Cl *x : ready) {
                     ClientGroup &grp = cg[(size_t)x->c][(size_t)x->gi];
@@ -956,7 +1002,7 @@ extern "C" int gen_server_drive(gen_server *s, int32_t n_clients, int32_t groups
                     x->next += gap(x->c, x->k++);
                 }
             }
-            s->cv_sched.notify_one();
+            if (s->sched_idle.load(std::memory_order_acquire)) s->cv_sched.notify_one();
         }
         for (auto &x : cl)
             for (auto &grp : cg[(size_t)x.c])
