@@ -335,6 +335,26 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
                          "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, step_s)}}
 
 
+def served_roofline(frames_per_s: float, specs, key: str | None = None) -> dict:
+    """Whole-job served throughput against the HBM peak: frames/s x the
+    pooled step's algorithmic bytes per frame of the served envs (a served
+    group is a pool: descriptor read and step counter included).  With a
+    counter record for `key` taken on the current kernel source, also the
+    measured DRAM bytes per frame."""
+    bpf = pool_bytes_per_frame(specs)
+    ach = frames_per_s * bpf / 1e9
+    out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_frame": bpf, "kernel": "k_serve", "traffic_bytes_per_frame": None}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(key) if key else None
+    except (OSError, ValueError):
+        rec = None
+    if rec and rec.get("kernel_hash") == kernel_hash():
+        out["traffic_bytes_per_frame"] = rec.get("bytes_per_frame")
+    return out
+
+
 def run_served_c2(gen, torch, duration_s: float) -> dict:
     """The headline workload served: its 65,536 envs as 256 groups of 256,
     one closed-loop client per group issuing back-to-back step requests."""
@@ -353,10 +373,12 @@ def run_served_c2(gen, torch, duration_s: float) -> dict:
     srv.close_server()
     del srv
     torch.cuda.empty_cache()
+    fps = rep["frames"] / rep["wall_s"]
     return {"workload": "served-" + wl.name + " (256 groups x 256 envs, 256 closed-loop clients)",
-            "frames_per_s": rep["frames"] / rep["wall_s"], "requests": rep["requests"],
+            "frames_per_s": fps, "requests": rep["requests"],
             "lat_p50_us": rep["lat_p50_us"], "lat_p99_us": rep["lat_p99_us"],
-            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
+            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"],
+            "roofline": served_roofline(fps, specs, "served-" + wl.name)}
 
 
 def run_served_mix(gen, torch, duration_s: float) -> dict:
@@ -383,7 +405,8 @@ def run_served_mix(gen, torch, duration_s: float) -> dict:
             "resident_envs": int(sizes.sum()), "arena_gb": arena / 2 ** 30,
             "frames_per_s": rep["frames"] / rep["wall_s"], "requests": rep["requests"],
             "lat_p50_us": rep["lat_p50_us"], "lat_p99_us": rep["lat_p99_us"],
-            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"]}
+            "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"],
+            "roofline": served_roofline(rep["frames"] / rep["wall_s"], specs)}
 
 
 def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) -> dict:

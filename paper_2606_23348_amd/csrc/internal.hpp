@@ -72,12 +72,13 @@ struct ServeReq {
 // launch needs no host-to-device copy: the requests as indices into the
 // server's table of group records (device memory, one record per open
 // group, written when the group is admitted).
-constexpr uint32_t kServeMaxReqs = 1024;      // requests per launch
+constexpr uint32_t kServeMaxReqs = 512;       // requests per launch
 constexpr uint32_t kServeMaxGroups = 16384;   // open groups (16-bit indices)
 struct ServeLaunch {
     uint8_t *arena;
     const ServeReq *groups;
     uint32_t n_req;
+    uint32_t first[kServeMaxReqs];   // first workgroup of each request: 0, then running sums of n_envs
     uint16_t idx[kServeMaxReqs];
 };
 static_assert(sizeof(ServeReq) == 152, "group record size stated in generals.h");
@@ -167,8 +168,10 @@ hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, hipStrea
 
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);
-// Grid (max_envs, la.n_req): request y's env x per workgroup.
-hipError_t launch_serve(const ServeLaunch &la, uint32_t max_envs, uint32_t lds, hipStream_t stream);
+// One workgroup per env of the launch (total_envs = the requests' env
+// counts summed): workgroup b steps env b - first[i] of request i, the last
+// i with first[i] <= b.
+hipError_t launch_serve(const ServeLaunch &la, uint32_t total_envs, uint32_t lds, hipStream_t stream);
 int obs_variant(int HW, int P);
 hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, uint32_t nwv, hipStream_t stream);
 hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream);

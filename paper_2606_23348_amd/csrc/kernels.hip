@@ -1214,10 +1214,10 @@ hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 
 // ---------------------------------------------------------------- served batches
 // One launch steps the envs of many requests (each request = one step of a
-// group, a pool of its own).  The grid is (largest request's env count) x
-// (requests): workgroup (x, y) steps env x of request y, or exits at once
-// when request y has fewer envs -- one wave-uniform load of the request
-// instead of a search over the table.
+// group, a pool of its own), one workgroup per env of the launch; a
+// workgroup finds its request by a binary search over the requests' first
+// workgroups (at most 9 scalar loads from the argument segment), so no
+// workgroup is launched for nothing when request sizes differ.
 // Buffers are addressed as arena + offset so that every pointer derives from
 // a kernel argument (global address space, scalar base + vector offset).
 // The request list travels in the kernel argument (scalar loads from the
@@ -1229,8 +1229,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 {
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *const arena = la.arena;
-    const ServeReq &r = la.groups[la.idx[blockIdx.y]];
-    const uint32_t slot = blockIdx.x;
+    // the request holding this workgroup: binary search over the ascending
+    // first[] (wave-uniform, scalar loads), first[lo] <= b < first[hi]
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = la.n_req;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (la.first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const ServeReq &r = la.groups[la.idx[lo]];
+    const uint32_t slot = b - la.first[lo];
     if (slot >= r.n_envs) return;
     PoolArgs a;
     a.prm = r.prm;
@@ -1255,10 +1264,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     pool_env<K_STEP, true>(a, smem, slot);
 }
 
-hipError_t launch_serve(const ServeLaunch &la, uint32_t max_envs, uint32_t lds, hipStream_t stream)
+hipError_t launch_serve(const ServeLaunch &la, uint32_t total_envs, uint32_t lds, hipStream_t stream)
 {
-    if (la.n_req == 0 || la.n_req > kServeMaxReqs) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_serve, dim3(max_envs, la.n_req), dim3(kWave), lds, stream, la);
+    if (la.n_req == 0 || la.n_req > kServeMaxReqs || total_envs == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_serve, dim3(total_envs), dim3(kWave), lds, stream, la);
     return hipGetLastError();
 }
 

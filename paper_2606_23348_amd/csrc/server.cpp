@@ -518,7 +518,7 @@ void scheduler(gen_server *sp)
         uint32_t n_req = 0;
         if (launch_now) {
             Slot &sl = *free_slot;
-            uint32_t wg = 0, lds = 0, max_envs = 0;
+            uint32_t wg = 0, lds = 0;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
                 Ticket *tk = ticket_of(s, it->ticket);
                 if (tk == nullptr || tk->status != 1) {
@@ -536,9 +536,9 @@ void scheduler(gen_server *sp)
                 if (g.busy || (s.max_batch_envs && n_req > 0 && wg + (uint32_t)g.n_envs > s.max_batch_envs)) { ++it; continue; }
                 g.busy = true;
                 sl.la.idx[n_req] = (uint16_t)g.tidx;
+                sl.la.first[n_req] = wg;
                 sl.reqs.emplace_back(it->ticket, &g);
                 wg += (uint32_t)g.n_envs;
-                max_envs = std::max(max_envs, (uint32_t)g.n_envs);
                 lds = std::max(lds, g.pool->lds_per_wave);
                 ++n_req;
                 it = s.queue.erase(it);
@@ -551,7 +551,7 @@ void scheduler(gen_server *sp)
                 s.st_launch_envs += wg;
                 sl.la.n_req = n_req;
                 lk.unlock();
-                hipError_t e = gen::launch_serve(sl.la, max_envs, lds, sl.stream);
+                hipError_t e = gen::launch_serve(sl.la, wg, lds, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
                 if (e != hipSuccess) {
                     lk.lock();
