@@ -435,7 +435,7 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) 
     key = wl.name + ("-padded" if obs_layout else "")       # counter records are per layout
     del b
     torch.cuda.empty_cache()
-    return {"workload": wl.name, "obs_layout": "planes padded to 32 bytes" if obs_layout else "dense [E,P,8,H,W]",
+    return {"workload": wl.name, "obs_layout": "planes padded to 32 bytes (64 above 2 players)" if obs_layout else "dense [E,P,8,H,W]",
             "steps": steps, "warmup": warmup, "frames_per_s": wl.n_envs * steps / elapsed,
             "step_kernel_ms_mean": avg * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

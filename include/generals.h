@@ -92,10 +92,12 @@ typedef struct gen_params {
     int32_t obs_layout;         /* observation layout of the plain-batch calls (gen_step,
                                    gen_step_sample, gen_observe, gen_reset): 0 = dense
                                    uint8 [E][P][8][H][W]; 1 = each plane H*W bytes then
-                                   zero bytes up to a multiple of 32, uint8 [E][P][8][PS]
-                                   with PS = (H*W + 31) & ~31 (the same as 0 when H*W is
-                                   a multiple of 32).  1 lets every env's planes be written
-                                   with aligned streaming stores.  Pools always use 1. */
+                                   zero bytes up to a multiple of 32 (of 64 with more
+                                   than 2 players), uint8 [E][P][8][PS] with
+                                   PS = (H*W + 31) & ~31, or (H*W + 63) & ~63 when P > 2
+                                   (the same as 0 when H*W is a multiple of that).  1 lets
+                                   every env's planes be written with aligned streaming
+                                   stores.  Pools always use 1. */
     int32_t reserved[3];        /* must be zero */
 } gen_params;
 
@@ -286,8 +288,9 @@ int gen_set_state(const gen_state *st, const gen_host_state *h, void *stream);
  * (layout private to the library), observations, actions and rewards in
  * ragged caller buffers at the offsets gen_pool_offsets reports.  An env's
  * observation block holds its [P][8] planes (channels as in gen_step), each
- * plane H*W bytes row-major followed by zero bytes up to a multiple of 32
- * (plane stride PS = (H*W + 31) & ~31, so plane (p, ch) starts at byte
+ * plane H*W bytes row-major followed by zero bytes up to a multiple of 32,
+ * or of 64 for envs of more than 2 players (plane stride PS = (H*W + 31) & ~31,
+ * or (H*W + 63) & ~63 when P > 2, so plane (p, ch) starts at byte
  * (8p + ch) * PS of the block): every plane starts on a 32-byte sector and
  * the whole block is written with aligned 4-byte streaming stores.  The random
  * actor of a pool draws with each env's own step counter (0 at reset, +1

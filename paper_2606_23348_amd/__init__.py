@@ -347,7 +347,7 @@ class Batch:
         P = lay.n_players
         self.n_envs, self.H, self.W, self.mode, self.P = n_envs, H, W, mode, P
         self.padded = params is not None and params.obs_layout == 1
-        self.PS = plane_stride(H, W) if self.padded else H * W
+        self.PS = plane_stride(H, W, P) if self.padded else H * W
         # zero-filled, so alignment padding the library never writes is deterministic
         self.buf = torch.zeros(lay.bytes, dtype=torch.uint8, device=device)
         obs_shape = (n_envs, P, 8, self.PS) if self.padded else (n_envs, P, 8, H, W)
@@ -565,15 +565,17 @@ class Pool:
         return slice(a, a + int(self.specs["P"][e]))
 
 
-def plane_stride(H: int, W: int) -> int:
-    """Bytes between two planes of a pool env's observation block."""
-    return (H * W + 31) & ~31
+def plane_stride(H: int, W: int, P: int) -> int:
+    """Bytes between two planes of a padded observation block (pool envs,
+    plain batches with obs_layout 1): H*W rounded up to 32 bytes, to 64 with
+    more than 2 players."""
+    return (H * W + 63) & ~63 if P > 2 else (H * W + 31) & ~31
 
 
 def pool_env_obs(obs, off: int, H: int, W: int, P: int):
     """The [P, 8, H*W] observation of the pool env whose block starts at byte
     `off` of a ragged observation buffer (torch tensor or numpy array)."""
-    PS = plane_stride(H, W)
+    PS = plane_stride(H, W, P)
     return obs[off:off + P * 8 * PS].reshape(P, 8, PS)[:, :, :H * W]
 
 

@@ -85,7 +85,7 @@ gen::Geom geom_of(const gen_state &st)
     g.NW = (g.HW + 63) / 64;
     g.magic_w = (uint32_t)(((1u << 20) + (uint32_t)st.W - 1) / (uint32_t)st.W);
     g.magic_hw = (uint32_t)(((uint64_t(1) << 32) + (uint64_t)g.HW - 1) / (uint64_t)g.HW);
-    g.PS = st.params.obs_layout == 1 ? gen::pool_plane_stride(g.HW) : g.HW;
+    g.PS = st.params.obs_layout == 1 ? gen::pool_plane_stride(g.HW, g.P) : g.HW;
     return g;
 }
 
@@ -124,7 +124,7 @@ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 int check_obs_ptr(const gen_state &st, const uint8_t *d_obs)
 {
     if (d_obs == nullptr) return GEN_OK;
-    const uint64_t PS = st.params.obs_layout == 1 ? (uint64_t)gen::pool_plane_stride(st.H * st.W)
+    const uint64_t PS = st.params.obs_layout == 1 ? (uint64_t)gen::pool_plane_stride(st.H * st.W, st.n_players)
                                                   : (uint64_t)st.H * st.W;
     const uint64_t B = (uint64_t)st.n_players * 8 * PS;
     const uintptr_t need = (B % 16 == 0) ? 16 : 8;
@@ -713,7 +713,7 @@ int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_
         d.pad8 = 0;
         d.env = (uint32_t)i;
         cells += (uint64_t)st.stride;
-        obs16 += ((uint64_t)st.n_players * 8 * (uint64_t)gen::pool_plane_stride(sp.H * sp.W) + 15) / 16;
+        obs16 += ((uint64_t)st.n_players * 8 * (uint64_t)gen::pool_plane_stride(sp.H * sp.W, st.n_players) + 15) / 16;
         acts += (uint64_t)st.n_players;
         pl->work[(size_t)i] = (uint64_t)st.n_players * sp.H * sp.W;
         if (st.stride > max_s) max_s = st.stride;

@@ -36,18 +36,27 @@ struct Geom {
     int PS;              // observation plane stride in bytes (HW, or HW padded to 32 bytes)
 };
 
-// Plane stride of a pool env's observation block: H*W rounded up to a
-// multiple of 32 bytes, so every plane starts on its own 32-byte sector and
-// nontemporal stores never write part of a sector another plane shares
-// (measured on the mixed pool: 365 us per step with the unaligned-plane
-// writer, 291 us with planes rounded to 4 bytes, 283 us rounded to 32).
-__host__ __device__ __forceinline__ int pool_plane_stride(int HW) { return (HW + 31) & ~31; }
+// Plane stride of a padded observation block (pool envs; plain batches with
+// obs_layout 1): H*W rounded up to a multiple of 32 bytes, so every plane
+// starts on its own 32-byte sector and nontemporal stores never write part
+// of a sector another plane shares (measured on the mixed pool: 365 us per
+// step with the unaligned-plane writer, 291 us with planes rounded to 4
+// bytes, 283 us rounded to 32).  Envs of more than 2 players round to 64
+// bytes: with 32 or more planes per env, planes that end in the middle of
+// a 64-byte block cost 30-45% of the step (131,072-env pools, FFA-4 436 ->
+// 304 us, 2v2 454 -> 308 us; 20x20 2v2, 400-byte planes: 188 -> 101 us);
+// 1v1 envs and the mixed pool measured the same either way, and 64 bytes
+// for every env slowed the served mix by 5%.
+__host__ __device__ __forceinline__ int pool_plane_stride(int HW, int P)
+{
+    return P > 2 ? (HW + 63) & ~63 : (HW + 31) & ~31;
+}
 
 // Per-env descriptor of a batched pool (32 bytes, device resident).
 struct PoolDesc {
     uint32_t cell_off;   // first cell of the env in the owner/type/army arrays (multiple of 16)
     uint32_t obs_off16;  // offset of the env's observation block ([P][8] planes of
-                         // pool_plane_stride(H*W) bytes), in 16-byte units
+                         // pool_plane_stride(H*W, P) bytes), in 16-byte units
     uint32_t act_off;    // first int32 of the env's actions and rewards
     uint32_t magic_w, magic_hw;
     uint8_t H, W, mode, P;

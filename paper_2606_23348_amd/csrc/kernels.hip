@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint3
     g.NW = (g.HW + 63) >> 6;
     g.magic_w = d.magic_w;
     g.magic_hw = d.magic_hw;
-    g.PS = pool_plane_stride(g.HW);
+    g.PS = pool_plane_stride(g.HW, g.P);
     uint8_t *obs = a.obs != nullptr ? a.obs + (size_t)d.obs_off16 * 16 : nullptr;
     if (wave > 0) {
         // exactly one barrier, matching the one wave 0 passes after the vision

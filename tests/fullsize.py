@@ -151,7 +151,7 @@ class PoolBuckets:
             cfg = oracle.Config(H=H, W=W, mode=mode, P=P, cities_min=cmin, cities_max=cmax, min_general_dist=dmin,
                                 seed=seed, env_ids=(np.uint64(env_base) + idx.astype(np.uint64)), **common_kw)
             self.buckets.append({"idx": idx, "cfg": cfg, "cells": cell_off[idx], "obs": obs_off[idx].astype(np.int64),
-                                 "act": act_off[idx].astype(np.int64), "HW": H * W, "PS": (H * W + 31) & ~31, "P": P})
+                                 "act": act_off[idx].astype(np.int64), "HW": H * W, "PS": (H * W + 63) & ~63 if P > 2 else (H * W + 31) & ~31, "P": P})
         self.states = list(pool.map(lambda bk: oracle.reset(bk["cfg"], len(bk["idx"]))[0], self.buckets))
         self.next_act: list[np.ndarray | None] = [None] * len(self.buckets)
 

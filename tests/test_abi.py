@@ -141,7 +141,7 @@ def test_pool_plan_host_side(L):
     obs = np.zeros(3, np.uint64)
     act = np.zeros(3, np.uint32)
     assert L.gen_pool_offsets(h, obs.ctypes.data, act.ctypes.data) == 0
-    sizes = [2 * 8 * 128, 4 * 8 * 640, 3 * 8 * 32]      # planes padded to a multiple of 32 bytes
+    sizes = [2 * 8 * 128, 4 * 8 * 640, 3 * 8 * 64]      # planes padded to 32 bytes, 64 with more than 2 players
     assert obs.tolist() == [0, (sizes[0] + 15) // 16 * 16, ((sizes[0] + 15) // 16 + (sizes[1] + 15) // 16) * 16]
     assert act.tolist() == [0, 2, 6]
     assert info.obs_bytes == sum((s + 15) // 16 * 16 for s in sizes)

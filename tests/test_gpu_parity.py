@@ -65,7 +65,7 @@ def run_parity(gen, H, W, mode, P, E, steps, seed, actor_seed, prm, check_every=
     compare actions, rewards, dones, observations and full state.  With
     fused=True the GPU runs gen_step_sample (step + next actions in one
     launch) and its actions are compared with the oracle's next draw.
-    obs_layout=1: the GPU writes planes padded to 32 bytes."""
+    obs_layout=1: the GPU writes planes padded to 32 bytes (64 with more than 2 players)."""
     import torch
     params = gparams(gen, mode, P, dict(prm, obs_layout=obs_layout))
     b = gen.Batch(E, H, W, mode, params, seed=seed, scoreboard=scoreboard)
@@ -173,7 +173,7 @@ def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
 ])
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 def test_trajectory_parity_padded_planes(gen, H, W, mode, P, E, steps, fused):
-    """obs_layout 1 (planes padded to 32 bytes, every plane written by the
+    """obs_layout 1 (planes padded to 32 or 64 bytes, every plane written by the
     dword writer): the same observation bytes, zero padding."""
     prm = dict(mountain_thresh=workloads.mountain_thresh(1, 5), cities_min=min(2, H * W // 8),
                cities_max=min(6, H * W // 4), min_general_dist=min(5, (H + W) // 3), auto_reset=1)

@@ -58,7 +58,7 @@ def check_env(pool, e, cfg, ost, obs_cpu, act_cpu, where, next_act=None):
     P, H, W = cfg.P, cfg.H, cfg.W
     assert np.array_equal(gen.pool_env_obs(obs_cpu, o, H, W, P).reshape(1, P, 8, H, W), oracle.observe(cfg, ost)), \
         f"{where}: env {e} obs"
-    PS = gen.plane_stride(H, W)
+    PS = gen.plane_stride(H, W, P)
     assert not obs_cpu[o:o + P * 8 * PS].reshape(P * 8, PS)[:, H * W:].any(), f"{where}: env {e} plane padding"
     if next_act is not None:
         sl = pool.env_slice(e)
