@@ -52,6 +52,22 @@ __host__ __device__ __forceinline__ int pool_plane_stride(int HW, int P)
     return P > 2 ? (HW + 63) & ~63 : (HW + 31) & ~31;
 }
 
+// Workgroup b of an n-workgroup grid -> the env it steps, so that the
+// workgroups the dispatcher hands to one XCD (b mod 8, round robin) take a
+// contiguous range of envs: neighbouring envs share 64-byte blocks of the
+// scalar records, rewards, done flags and actions, and their partial writes
+// then meet in the same XCD's L2 instead of reaching memory separately from
+// different XCDs (plain batches, where every env has the same work: 1v1
+// 24x24 144.3 -> 140.9 us, FFA-8 25x25 144.6 -> 139.4 us per step; the
+// 38-channel features 3,271 -> 3,255 us).  Not
+// for pools and served launches: their envs differ in work, and contiguous
+// ranges unbalance the XCDs (served mix 3% slower).
+__device__ __forceinline__ uint32_t xcd_env(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b & 7u, i = b >> 3, per = n >> 3, rem = n & 7u;
+    return x * per + min(x, rem) + i;
+}
+
 // Per-env descriptor of a batched pool (32 bytes, device resident).
 struct PoolDesc {
     uint32_t cell_off;   // first cell of the env in the owner/type/army arrays (multiple of 16)

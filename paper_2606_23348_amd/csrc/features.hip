@@ -69,7 +69,7 @@ __global__ __launch_bounds__(512) void k_features(FeatArgs a)
 {
     constexpr int kOut = NT ? kNT : 0;        // cache policy of the feature and token stores
     extern __shared__ __align__(16) uint8_t smem[];
-    const int e = blockIdx.x, lane = lane_id();
+    const int e = (int)xcd_env(blockIdx.x, gridDim.x), lane = lane_id();   // see xcd_env
     const int tid = (int)threadIdx.x, nt = (int)blockDim.x;   // nt = 64 x (waves per env)
     const bool wave0 = readfirst(tid >> 6) == 0;
     const Geom g = a.g;

@@ -989,7 +989,7 @@ template <int KIND, int OBSV, bool SB, bool ACT, int NWV>
 __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB || OBSV != OBS_QUAD) ? 1 : 8, 8))) void k_env(EnvArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int e = blockIdx.x;
+    const int e = (int)xcd_env(blockIdx.x, gridDim.x);
     const Geom g = a.g;
     const size_t cell0 = (size_t)e * g.S;
     EnvIO io;
