@@ -1105,7 +1105,7 @@ __global__ __launch_bounds__(256) void k_pool(PoolArgs a)
         for (uint32_t slot = a.slot_begin + blockIdx.x * a.wpg + wave; slot < a.slot_end; slot += gridDim.x * a.wpg)
             pool_env<KIND, ACT>(a, mine, slot);
     } else {
-        const uint32_t slot = a.slot_begin + blockIdx.x * a.wpg + wave;
+        const uint32_t slot = a.slot_begin + xcd_chunk32(blockIdx.x, gridDim.x) * a.wpg + wave;
         if (slot < a.slot_end) pool_env<KIND, ACT>(a, mine, slot);
     }
 }
