@@ -437,7 +437,7 @@ typedef struct gen_server_stats {
  * use; n_launch_streams: launches in flight (1..4); max_batch_envs: cap on
  * envs per launch (0 = no cap).  Starts the scheduler thread.  The server
  * keeps one record per open group in a table carved from the arena at
- * creation (16,384 records of 152 bytes); a launch carries at most 512
+ * creation (16,384 records of 192 bytes); a launch carries at most 512
  * requests, the list itself passed as the kernel argument (no copy). */
 int gen_server_create(void *d_arena, uint64_t arena_bytes, int32_t n_launch_streams, int32_t max_batch_envs,
                       gen_server **out);

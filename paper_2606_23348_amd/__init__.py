@@ -335,6 +335,14 @@ def gen_set_state(st: gen_state, h: dict, stream=None):
     _check(lib().gen_set_state(ctypes.byref(st), ctypes.byref(hs), _stream(stream)))
 
 
+def _filled(device):
+    """Wait for the zero fills torch just queued on its current stream: the
+    library may be called on another stream, which would not wait for them
+    (and a late fill would overwrite what the library wrote)."""
+    import torch
+    torch.cuda.current_stream(torch.device(device)).synchronize()
+
+
 class Batch:
     """Device tensors of one batch of identical envs (torch allocates; the
     library computes).  Convenience only: every method is one library call."""
@@ -358,6 +366,7 @@ class Batch:
         self.land = torch.zeros((n_envs, P), dtype=torch.int32, device=device) if scoreboard else None
         self.army = torch.zeros((n_envs, P), dtype=torch.int64, device=device) if scoreboard else None
         self.feat = self.fmem = self.tokens = None   # 38-channel features, allocated by features()
+        _filled(self.buf.device)
         self.st = gen_reset(seed, env_base, n_envs, H, W, mode, params, self.buf, self.obs, stream)
 
     def obs_dense(self) -> np.ndarray:
@@ -393,8 +402,10 @@ class Batch:
             self.fmem = torch.zeros(gen_feat_mem_bytes(self.st), dtype=torch.uint8, device=dev)
             self.feat = torch.zeros((self.n_envs, self.P, FEAT_CHANNELS, self.H, self.W), dtype=torch.float32,
                                     device=dev)
+            _filled(dev)
         if tokens and self.tokens is None:
             self.tokens = torch.zeros((self.n_envs, self.P, 2, TOKEN_WINDOW), dtype=torch.float32, device=dev)
+            _filled(dev)
         gen_features(self.st, self.fmem, self.feat, self.tokens if tokens else None, stream)
 
     def rollout(self, n_steps: int, actor_seed: int, step0: int, tokens: bool = False, out: dict | None = None,
@@ -407,6 +418,7 @@ class Batch:
         dev = self.buf.device
         if self.fmem is None:
             self.fmem = torch.zeros(gen_feat_mem_bytes(self.st), dtype=torch.uint8, device=dev)
+            _filled(dev)
         E, P, T = self.n_envs, self.P, n_steps
         if out is None:
             out = {"feat": torch.empty((T, E, P, FEAT_CHANNELS, self.H, self.W), dtype=torch.float32, device=dev),
@@ -469,6 +481,7 @@ class Pool:
         self.actions = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
         self.rewards = torch.zeros(info.n_actions, dtype=torch.int32, device=device)
         self.dones = torch.zeros(self.n, dtype=torch.uint8, device=device)
+        _filled(device)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -66,6 +66,11 @@ struct ServeReq {
     uint64_t seed, env_base, actor_seed;
     GenParamsDev prm;
     uint32_t n_envs, actor;
+    // uniform != 0: every env of the group has tmpl's shape and settings,
+    // cells_per_env cells and obs16_per_env 16-byte units of observation,
+    // in env order, so the kernel derives each env's descriptor
+    PoolDesc tmpl;
+    uint32_t uniform, cells_per_env, obs16_per_env;
 };
 
 // One served launch, passed by value as the kernel argument so that a
@@ -81,7 +86,7 @@ struct ServeLaunch {
     uint32_t first[kServeMaxReqs];   // first workgroup of each request: 0, then running sums of n_envs
     uint16_t idx[kServeMaxReqs];
 };
-static_assert(sizeof(ServeReq) == 152, "group record size stated in generals.h");
+static_assert(sizeof(ServeReq) == 192, "group record size stated in generals.h");
 static_assert(sizeof(ServeLaunch) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // One env's block of the feature memory (38-channel features), byte offsets:

@@ -1038,9 +1038,9 @@ __global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu((SB ||
 // One pool env on the calling wave (slot = position in the work list;
 // wave = the wave's index within the env, of nwv).
 template <int KIND, bool ACT>
-__device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint32_t slot, int nwv = 1, int wave = 0)
+__device__ __forceinline__ void pool_env_d(const PoolArgs &a, uint8_t *smem, const PoolDesc &d, int nwv = 1,
+                                           int wave = 0)
 {
-    const PoolDesc d = a.desc[slot];
     const uint32_t e = d.env;
     Geom g;
     g.H = d.H;
@@ -1082,6 +1082,12 @@ __device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint3
     io.use_tick = true;
     io.nwv = nwv;
     env_body<KIND, OBS_PADDED, false, ACT>(smem, g, prm, a.seed, a.actor_seed, io);
+}
+
+template <int KIND, bool ACT>
+__device__ __forceinline__ void pool_env(const PoolArgs &a, uint8_t *smem, uint32_t slot, int nwv = 1, int wave = 0)
+{
+    pool_env_d<KIND, ACT>(a, smem, a.desc[slot], nwv, wave);
 }
 
 // PERSIST = false: one env per wave (per workgroup with NWV = 2), the grid
@@ -1261,7 +1267,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     a.rewards = reinterpret_cast<int32_t *>(arena + r.off_rewards);
     a.dones = arena + r.off_dones;
     a.obs = r.off_obs != ~0ull ? arena + r.off_obs : nullptr;
-    pool_env<K_STEP, true>(a, smem, slot);
+    if (r.uniform) {
+        // every env of the group has the template's shape and settings: its
+        // descriptor follows from the slot (no dependent load of it)
+        PoolDesc d = r.tmpl;
+        d.cell_off = slot * r.cells_per_env;
+        d.obs_off16 = slot * r.obs16_per_env;
+        d.act_off = slot * d.P;
+        d.env = slot;
+        pool_env_d<K_STEP, true>(a, smem, d);
+    } else {
+        pool_env<K_STEP, true>(a, smem, slot);
+    }
 }
 
 hipError_t launch_serve(const ServeLaunch &la, uint32_t total_envs, uint32_t lds, hipStream_t stream)

@@ -320,6 +320,22 @@ void fill_req(const gen_server &s, const Group &g, gen::ServeReq *r)
     r->prm = gen::prm_of(pl.common);
     r->n_envs = (uint32_t)pl.n;
     r->actor = g.actor ? 1u : 0u;
+    // one shape and one set of settings for the whole group, envs in their
+    // own order: the kernel derives every env's descriptor from the first
+    const gen::PoolDesc &d0 = pl.desc[0];
+    const uint32_t cells = pl.n > 1 ? pl.desc[1].cell_off : 0, ob16 = pl.n > 1 ? pl.desc[1].obs_off16 : 0;
+    bool uni = true;
+    for (int32_t i = 0; i < pl.n && uni; ++i) {
+        const gen::PoolDesc &d = pl.desc[(size_t)i];
+        uni = pl.order[(size_t)i] == (uint32_t)i && d.H == d0.H && d.W == d0.W && d.mode == d0.mode && d.P == d0.P &&
+              d.cmin == d0.cmin && d.cmax == d0.cmax && d.dmin == d0.dmin && d.env == (uint32_t)i &&
+              d.cell_off == (uint32_t)i * cells && d.obs_off16 == (uint32_t)i * ob16 &&
+              d.act_off == (uint32_t)i * d0.P;
+    }
+    r->tmpl = d0;
+    r->uniform = uni ? 1u : 0u;
+    r->cells_per_env = cells;
+    r->obs16_per_env = ob16;
     (void)s;
 }
 

@@ -34,6 +34,15 @@ def group_specs(n, seed, lo=6, hi=20):
             "min_general_dist": np.minimum((H + W) // 4, 8)}
 
 
+def uniform_specs(n, H, W, mode, P):
+    """n envs of one shape and one set of settings (the server derives their
+    descriptors from the first env's instead of loading them)."""
+    cmax = min(H * W // 8, 8)
+    return {"H": np.full(n, H), "W": np.full(n, W), "mode": np.full(n, mode), "P": np.full(n, P),
+            "cities_min": np.full(n, cmax // 2), "cities_max": np.full(n, cmax),
+            "min_general_dist": np.full(n, min((H + W) // 4, 8))}
+
+
 def common(gen):
     return gen.make_params(0, 2, mountain_thresh=workloads.mountain_thresh(1, 5), city_army_min=40,
                            city_army_max=50, auto_reset=1)
@@ -57,6 +66,7 @@ def snapshot(srv, gid, specs):
 
 def test_server_mix_vs_alone(gen):
     specs = [group_specs(n, 100 + i) for i, n in enumerate((40, 7, 130, 64, 1, 90))]
+    specs += [uniform_specs(70, 24, 24, 0, 2), uniform_specs(33, 13, 11, 1, 4), uniform_specs(20, 9, 7, 2, 5)]
     bases = np.cumsum([0] + [len(s["H"]) for s in specs])
     T = 25
     results = {}
