@@ -176,7 +176,8 @@ uint32_t lds_bytes_for(int S, int P);
 // One workgroup per env of the launch (total_envs = the requests' env
 // counts summed): workgroup b steps env b - first[i] of request i, the last
 // i with first[i] <= b.
-hipError_t launch_serve(const ServeLaunch &la, uint32_t total_envs, uint32_t lds, hipStream_t stream);
+// all_uniform: every request's group record has uniform set.
+hipError_t launch_serve(const ServeLaunch &la, uint32_t total_envs, uint32_t lds, bool all_uniform, hipStream_t stream);
 int obs_variant(int HW, int P);
 hipError_t launch_pool(const PoolArgs &a, int kind, bool act, uint32_t grid, uint32_t nwv, hipStream_t stream);
 hipError_t launch_step(const EnvArgs &a, int n_envs, hipStream_t stream);

@@ -535,6 +535,7 @@ void scheduler(gen_server *sp)
         if (launch_now) {
             Slot &sl = *free_slot;
             uint32_t wg = 0, lds = 0;
+            bool all_uni = true;
             for (auto it = s.queue.begin(); it != s.queue.end() && n_req < s.max_reqs;) {
                 Ticket *tk = ticket_of(s, it->ticket);
                 if (tk == nullptr || tk->status != 1) {
@@ -556,6 +557,7 @@ void scheduler(gen_server *sp)
                 sl.reqs.emplace_back(it->ticket, &g);
                 wg += (uint32_t)g.n_envs;
                 lds = std::max(lds, g.pool->lds_per_wave);
+                all_uni = all_uni && g.req.uniform != 0;
                 ++n_req;
                 it = s.queue.erase(it);
                 s.n_queued.fetch_sub(1, std::memory_order_release);
@@ -567,7 +569,7 @@ void scheduler(gen_server *sp)
                 s.st_launch_envs += wg;
                 sl.la.n_req = n_req;
                 lk.unlock();
-                hipError_t e = gen::launch_serve(sl.la, wg, lds, sl.stream);
+                hipError_t e = gen::launch_serve(sl.la, wg, lds, all_uni, sl.stream);
                 if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
                 if (e != hipSuccess) {
                     lk.lock();
