@@ -1228,15 +1228,16 @@ hipError_t launch_observe(const EnvArgs &a, int n_envs, hipStream_t stream)
 // a kernel argument (global address space, scalar base + vector offset).
 // The request list travels in the kernel argument (scalar loads from the
 // argument segment), the group records stay resident in the arena.
-// Registers are budgeted for 8 waves per SIMD, the occupancy the LDS of the
-// boards up to 24x24 allows (measured 3% faster on served 24x24 1v1 groups
-// than the default budget of 7 waves).
 // UNI: every request of the launch is a uniform group (its record says so),
 // whose descriptors the kernel derives instead of loading; a launch with any
 // other group loads every descriptor (one copy of the step per kernel: with
 // both forms in one kernel the served mix ran 5-13% slower).
+// The uniform instance budgets registers for 8 waves per SIMD (uniform 24x24
+// 1v1 groups fit 8 in LDS); the other keeps the default budget, since the
+// LDS of its largest board limits it to fewer waves anyway (served mix
+// 401.5 -> 410 M frames/s without the 8-wave budget's spills).
 template <bool UNI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_serve(ServeLaunch la)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(UNI ? 8 : 1, 8))) void k_serve(ServeLaunch la)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *const arena = la.arena;
