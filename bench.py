@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2606_23348_amd/csrc/kernels.hip", "paper_2606_23348_amd/csrc/features.hip",
                   "paper_2606_23348_amd/csrc/device.hpp", "paper_2606_23348_amd/csrc/internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-EXTRAS = ("sustained", "step_alone", "features", "copy", "c3", "rollout", "served", "pool", "served_mix")
+EXTRAS = ("sustained", "step_alone", "features", "copy", "c1", "c3", "rollout", "served", "pool", "served_mix")
 
 
 _T0 = time.perf_counter()
@@ -620,6 +620,10 @@ def main() -> int:
     if "copy" in legs:
         log("copy ceiling")
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(gen, torch)
+    if "c1" in legs:
+        # 16 envs of 10x10: 16 workgroups on 256 CUs, bound by launch latency, not bytes
+        out["c1"] = run_plain_leg(gen, torch, workloads.C1, workloads.C1.steps, W)
+        out["c1"]["roofline"]["bound"] = "latency (16 workgroups)"
     if "c3" in legs:
         log("FFA-8 leg")
         out["c3"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W, obs_layout=1)
