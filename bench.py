@@ -444,7 +444,8 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) 
 
 
 def host_cores() -> int:
-    """Host cores this process may use (the GPU machine grants 16 per GPU)."""
+    """Host cores this process may use: its CPU affinity, at most 16 (the
+    host share of one GPU on the MI355X nodes this runs on)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

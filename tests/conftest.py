@@ -14,8 +14,9 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    """GPU tests are skipped (not failed) where no GPU is visible; on a GPU machine
-    a missing or unbuilt HIP library is a hard failure inside the tests."""
+    """GPU tests are skipped (not failed) where no GPU is visible; on a machine
+    with a GPU a missing or unbuilt HIP library is a hard failure inside the
+    tests."""
     try:
         import torch
         have_gpu = torch.cuda.is_available()
