@@ -466,7 +466,9 @@ int gen_server_buffers(gen_server *srv, uint64_t group, gen_group_buffers *out);
 int gen_server_submit(gen_server *srv, uint64_t group, uint64_t *ticket);
 /* GEN_OK when the step is done (its outputs are in the group's buffers),
  * GEN_EBUSY if timeout_us passed first (timeout_us < 0: wait forever),
- * GEN_ENOTFOUND for an unknown or already collected ticket. */
+ * GEN_ENOTFOUND for an unknown or already collected ticket (a finished
+ * ticket is kept until it is collected or 2^18 newer tickets were issued;
+ * a pending one is never dropped: submit returns GEN_EBUSY instead). */
 int gen_server_wait(gen_server *srv, uint64_t ticket, int64_t timeout_us);
 /* Waits for the group's work in flight, drops its queued requests (their
  * tickets fail with GEN_ENOTFOUND) and returns its memory to the arena,
