@@ -1,6 +1,6 @@
 """Throughput of the batched Generals.io environment step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3] [--obs-layout auto|dense|padded]
 
 One timed step is one pass of the whole hot path over every env of the
 workload, one launch of gen_step_sample: the environment step (moves,
@@ -409,11 +409,15 @@ def run_served_mix(gen, torch, duration_s: float) -> dict:
             "roofline": served_roofline(rep["frames"] / rep["wall_s"], specs)}
 
 
+LAYOUT_NAMES = {0: "dense [E,P,8,H,W]", 1: "planes padded to 32 bytes (64 above 2 players)"}
+
+
 def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) -> dict:
     """Another plain workload in the headline's form: `warmup` untimed
     fused launches, then `steps` timed back to back between one pair of HIP
     events on the launch stream.  obs_layout 1: observation planes padded to
-    32 bytes (the algorithmic bytes stay those of the dense planes)."""
+    32 bytes, 64 above 2 players (the algorithmic bytes stay those of the
+    dense planes)."""
     b = gen.Batch(wl.n_envs, wl.H, wl.W, wl.mode,
                   gen.make_params(wl.mode, wl.P, obs_layout=obs_layout, **wl.params()), seed=wl.seed)
     stream = torch.cuda.current_stream()
@@ -435,7 +439,7 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) 
     key = wl.name + ("-padded" if obs_layout else "")       # counter records are per layout
     del b
     torch.cuda.empty_cache()
-    return {"workload": wl.name, "obs_layout": "planes padded to 32 bytes (64 above 2 players)" if obs_layout else "dense [E,P,8,H,W]",
+    return {"workload": wl.name, "obs_layout": LAYOUT_NAMES[obs_layout],
             "steps": steps, "warmup": warmup, "frames_per_s": wl.n_envs * steps / elapsed,
             "step_kernel_ms_mean": avg * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -489,6 +493,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c2", choices=sorted(workloads.PLAIN))
+    ap.add_argument("--obs-layout", default="auto", choices=["auto", "dense", "padded"],
+                    help="observation planes of the timed workload: dense [E,P,8,H,W], or each plane padded "
+                         "to 32 bytes (64 above 2 players); auto pads them above 2 players, as pools do")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-envs", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=400)
@@ -525,7 +532,9 @@ def main() -> int:
     K = args.steps if args.steps is not None else wl.steps
     W = args.warmup
     E = wl.n_envs
-    params = gen.make_params(wl.mode, wl.P, **wl.params())
+    layout = 1 if args.obs_layout == "padded" or (args.obs_layout == "auto" and wl.P > 2) else 0
+    key = wl.name + ("-padded" if layout else "")            # counter records are per layout
+    params = gen.make_params(wl.mode, wl.P, obs_layout=layout, **wl.params())
     b = gen.Batch(E, wl.H, wl.W, wl.mode, params, seed=wl.seed)
     stream = torch.cuda.current_stream()
 
@@ -562,7 +571,7 @@ def main() -> int:
     step_ms = np.array([ev0[t].elapsed_time(ev1[t]) for t in range(n_lat)])
     by = step_bytes(wl)
     achieved = by["step"] * E / avg_step_s / 1e9
-    traffic = traffic_for(wl.name, E)
+    traffic = traffic_for(key, E)
     value = E * K / elapsed
 
     out = {
@@ -580,6 +589,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "n_envs": E, "H": wl.H, "W": wl.W,
                    "mode": {0: "1v1", 1: "2v2", 2: "ffa"}[wl.mode], "players": wl.P,
+                   "obs_layout": LAYOUT_NAMES[layout],
                    "step": "random legal actor + environment step, inputs resident in HBM",
                    "parallelism": "single GPU"},
         "step_kernel_ms": {"mean": avg_step_s * 1e3,
@@ -589,7 +599,7 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_env<STEP, actor fused> (gen_step_sample)",
                      "algorithmic_bytes_per_frame": by["step"],
-                     "frames_per_launch": E, "lds": lds_for(wl.name, avg_step_s)},
+                     "frames_per_launch": E, "lds": lds_for(key, avg_step_s)},
     }
     legs = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
     unknown = legs - set(EXTRAS)
