@@ -143,6 +143,35 @@ def copy_ceiling_gbs(gen, torch, n_bytes: int = 1 << 30, reps: int = 20) -> floa
     return gbs
 
 
+def spread_ceiling_gbs(gen, torch, ks=(1, 2, 3, 4, 5, 6, 8, 11), n_bytes: int = 8 << 30, reps: int = 20) -> dict:
+    """Bandwidth of the library's spread kernel (each 16-byte source chunk
+    written to k destination chunks, the copy's form; read + write bytes /
+    time) for k writes per read: the practical ceiling of a stream with a
+    step's own mix of reads and writes (1v1 24x24 writes about 3.5 times
+    what it reads, the mixed pool about 4.4, FFA-8 25x25 about 11).  8 GiB
+    written, so that even the k = 11 source (745 MB) is well beyond the
+    256 MB Infinity Cache (at 1 GiB the sources of k >= 4 fit in it)."""
+    dst = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    src = torch.empty(n_bytes, dtype=torch.uint8, device="cuda").fill_(1)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for k in ks:
+        n_src = -(-(n_bytes // 16) // k) * 16
+        for _ in range(3):
+            gen.gen_stream_spread(dst, src[:n_src], k, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            gen.gen_stream_spread(dst, src[:n_src], k, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[str(k)] = (n_bytes + n_src) * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_step_alone(b, wl, torch, stream, steps: int, first_step: int) -> dict:
     """gen_step by itself with the actions already in HBM: each step's
     actions come from a separate gen_sample_actions launch that lies
@@ -631,6 +660,8 @@ def main() -> int:
     if "copy" in legs:
         log("copy ceiling")
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(gen, torch)
+        out["roofline"]["writes_per_read"] = by["step_write"] / by["step_read"]
+        out["roofline"]["spread_ceiling_gbs"] = spread_ceiling_gbs(gen, torch)
     if "c1" in legs:
         # 16 envs of 10x10: 16 workgroups on 256 CUs, bound by launch latency, not bytes
         out["c1"] = run_plain_leg(gen, torch, workloads.C1, workloads.C1.steps, W)

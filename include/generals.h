@@ -526,10 +526,23 @@ int gen_get_envs_static(const gen_state *st, const int32_t *h_env_ids, int32_t n
 
 /* Measurement helper, not part of the step: copy `bytes` (a multiple of 16)
  * from d_src to d_dst (both 16-byte aligned device buffers, not overlapping)
- * with a plain streaming kernel of 16-byte nontemporal loads and stores.
- * Timed next to the step kernels, it gives the practical HBM ceiling of a
- * read-once / write-once stream. */
+ * with a plain streaming kernel (one 16-byte element per thread, plain
+ * loads, nontemporal stores).  Timed next to the step kernels, it gives the
+ * practical HBM ceiling of a read-once / write-once stream.  GEN_EINVAL on
+ * a null or misaligned buffer or a size not a multiple of 16. */
 int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream);
+
+/* Measurement helper, not part of the step: write `dst_bytes` (a multiple of
+ * 16, fewer than 2^32 16-byte chunks) to d_dst, chunk i being chunk
+ * floor(i / k) of d_src, which must hold ceil(dst_bytes / 16 / k) chunks
+ * (the caller owns both buffers: 16-byte aligned, on the current device, not
+ * overlapping).  k = 1 is the copy above; the kernel has the copy's form.  A
+ * stream writing k bytes per byte read: an env step writes 3.5 (1v1 24x24)
+ * to 11 (FFA-8 25x25) times what it reads, so timed at the step's ratio it
+ * gives the practical HBM ceiling of the step's mix of reads and writes.
+ * GEN_EINVAL on a null or misaligned buffer, a bad size or k = 0.  Asynchronous
+ * on `stream`. */
+int gen_stream_spread(void *d_dst, const void *d_src, uint64_t dst_bytes, uint32_t k, void *stream);
 
 #ifdef __cplusplus
 }

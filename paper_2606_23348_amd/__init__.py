@@ -141,6 +141,7 @@ def load_library(path: str) -> ctypes.CDLL:
     L.gen_pool_get_env.argtypes = [vp, i32, P(gen_host_state), vp]
     L.gen_pool_get_state.argtypes = [vp, P(gen_host_state), vp]
     L.gen_stream_copy.argtypes = [vp, vp, u64, vp]
+    L.gen_stream_spread.argtypes = [vp, vp, u64, ctypes.c_uint32, vp]
     L.gen_get_envs_static.argtypes = [P(gen_state), vp, i32, P(gen_host_state), vp]
     L.gen_server_create.argtypes = [vp, u64, i32, i32, P(vp)]
     L.gen_server_destroy.argtypes = [vp]
@@ -158,7 +159,7 @@ def load_library(path: str) -> ctypes.CDLL:
               "gen_observe", "gen_features", "gen_rollout", "gen_get_state", "gen_set_state", "gen_get_envs", "gen_pool_create",
               "gen_pool_destroy", "gen_pool_query", "gen_pool_offsets", "gen_pool_get_tuning",
               "gen_pool_set_tuning", "gen_pool_buckets", "gen_pool_set_buckets", "gen_pool_reset", "gen_pool_step", "gen_pool_capture", "gen_pool_replay",
-              "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_get_envs_static", "gen_server_create", "gen_server_destroy", "gen_server_open", "gen_server_wait_admitted",
+              "gen_pool_get_env", "gen_pool_get_state", "gen_stream_copy", "gen_stream_spread", "gen_get_envs_static", "gen_server_create", "gen_server_destroy", "gen_server_open", "gen_server_wait_admitted",
               "gen_server_buffers", "gen_server_submit", "gen_server_wait", "gen_server_close",
               "gen_server_report", "gen_server_set_batching", "gen_server_drive"):
         getattr(L, f).restype = ctypes.c_int
@@ -317,6 +318,14 @@ def gen_stream_copy(dst, src, stream=None):
     n = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == n
     _check(lib().gen_stream_copy(_ptr(dst), _ptr(src), n, _stream(stream)))
+
+
+def gen_stream_spread(dst, src, k: int, stream=None):
+    """Chunk i (16 bytes) of dst = chunk i // k of src: k bytes written per
+    byte read (src holds at least ceil(chunks of dst / k) chunks)."""
+    n = dst.numel() * dst.element_size()
+    assert k >= 1 and src.numel() * src.element_size() * k >= n
+    _check(lib().gen_stream_spread(_ptr(dst), _ptr(src), n, k, _stream(stream)))
 
 
 def gen_get_envs_static(st: gen_state, env_ids, stream=None) -> dict:

@@ -170,6 +170,7 @@ hipError_t launch_gather(const GatherArgs &a, uint32_t n_ids, hipStream_t stream
 // `device`, which must be the current device; looked up once per device.
 hipError_t static_staging(int device, void **out);
 hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, hipStream_t stream);
+hipError_t launch_stream_spread(void *dst, const void *src, uint32_t n16, uint32_t k, hipStream_t stream);
 
 uint32_t lds_bytes(const Geom &g);
 uint32_t lds_bytes_for(int S, int P);

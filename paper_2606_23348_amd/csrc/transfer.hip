@@ -94,8 +94,8 @@ hipError_t static_staging(int device, void **out)
 }
 
 // ---------------------------------------------------------------- streaming copy
-// dst[i] = src[i] over 16-byte elements, one element per thread, stores
-// nontemporal, a grid covering the buffer (no striding loop).  Measured
+// dst[i] = src[i] over 16-byte elements, one element per thread, plain
+// loads, nontemporal stores, a grid covering the buffer (no striding loop).  Measured
 // against the alternatives (more elements per thread, nontemporal loads,
 // a persistent striding grid) it moves the most bytes per second.  A
 // measurement of the achievable HBM rate of a read-once / write-once stream.
@@ -104,6 +104,24 @@ __global__ __launch_bounds__(256) void k_stream_copy(u32x4 *__restrict__ dst, co
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) __builtin_nontemporal_store(src[i], dst + i);
+}
+
+// dst[i] = src[i / k] (k >= 1, fewer than 2^32 elements): each source element
+// written to k consecutive destination elements, in the copy's form.  A
+// stream that writes k bytes for every byte it reads.
+__global__ __launch_bounds__(256) void k_stream_spread(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
+                                                        uint32_t n16, uint32_t k)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(src[i / k], dst + i);
+}
+
+hipError_t launch_stream_spread(void *dst, const void *src, uint32_t n16, uint32_t k, hipStream_t stream)
+{
+    const uint32_t grid = (uint32_t)(((uint64_t)n16 + 255) / 256);
+    hipLaunchKernelGGL(k_stream_spread, dim3(grid), dim3(256), 0, stream, static_cast<u32x4 *>(dst),
+                       static_cast<const u32x4 *>(src), n16, k);
+    return hipGetLastError();
 }
 
 hipError_t launch_stream_copy(void *dst, const void *src, uint64_t n16, hipStream_t stream)

@@ -102,6 +102,23 @@ def test_calls_reject_missing_state_without_touching_the_device(L):
     assert L.gen_reset(1, 0, 4, 10, 10, 0, None, None, 0, None, None, None) == gen.GEN_EINVAL
 
 
+def test_stream_helpers_reject_bad_arguments(L):
+    """The measurement copies check their arguments before any HIP call
+    (the fake addresses are never dereferenced)."""
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)
+    assert L.gen_stream_copy(None, b, 64, None) == gen.GEN_EINVAL
+    assert L.gen_stream_copy(ctypes.c_void_p((1 << 20) + 8), b, 64, None) == gen.GEN_EINVAL
+    assert L.gen_stream_copy(a, b, 65, None) == gen.GEN_EINVAL
+    assert L.gen_stream_copy(a, b, 0, None) == gen.GEN_OK
+    assert L.gen_stream_spread(a, None, 64, 2, None) == gen.GEN_EINVAL
+    assert L.gen_stream_spread(a, ctypes.c_void_p((1 << 21) + 4), 64, 2, None) == gen.GEN_EINVAL
+    assert L.gen_stream_spread(a, b, 40, 2, None) == gen.GEN_EINVAL
+    assert L.gen_stream_spread(a, b, 64, 0, None) == gen.GEN_EINVAL
+    assert "k >= 1" in gen.gen_last_error()
+    assert L.gen_stream_spread(a, b, 16 << 32, 1, None) == gen.GEN_EINVAL       # 2^32 chunks
+    assert L.gen_stream_spread(a, b, 0, 3, None) == gen.GEN_OK
+
+
 def test_reset_rejects_small_buffer(L):
     need = gen.gen_state_bytes(4, 10, 10, 0)
     fake = ctypes.c_void_p(1 << 20)                # never dereferenced: the size check comes first
