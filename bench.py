@@ -263,15 +263,43 @@ def run_rollout(gen, torch, n_envs: int = 512, n_steps: int = 512) -> dict:
             "ms_per_rollout": s_ * 1e3, "frames_per_s": n_envs * n_steps / s_, "launches": 2 * n_steps + 1}
 
 
-def pool_bytes_per_frame(specs) -> float:
-    """Mean algorithmic bytes per frame of the pooled step (same accounting as
-    step_bytes, per env shape; the scalar record also carries the step
-    counter, so 14 live bytes are written)."""
+def pool_rw_per_frame(specs) -> tuple:
+    """Mean algorithmic bytes read and written per frame of the pooled step
+    (same accounting as step_bytes, per env shape; the scalar record also
+    carries the step counter, so 14 live bytes are written)."""
     HW = specs["H"].astype(np.int64) * specs["W"].astype(np.int64)
     P = specs["P"].astype(np.int64)
     read = HW * 6 + 32 + 4 * P + 32          # + the env's 32-byte descriptor
     write = HW * 5 + P * 8 * HW + 4 * P + 1 + 14 + 4 * P
-    return float((read + write).mean())
+    return float(read.mean()), float(write.mean())
+
+
+def pool_bytes_per_frame(specs) -> float:
+    return sum(pool_rw_per_frame(specs))
+
+
+_SPREAD = {}          # k writes per read -> GB/s, filled by the copy leg
+
+
+def practical(achieved_gbs: float, writes_per_read: float):
+    """The achieved rate against the practical ceiling of a stream with the
+    same ratio of writes to reads (the spread kernel's table, linear between
+    its points, the last point beyond them); None without the copy leg."""
+    if not _SPREAD:
+        return None
+    pts = sorted((int(k), v) for k, v in _SPREAD.items())
+    r = writes_per_read
+    if r <= pts[0][0]:
+        ceil = pts[0][1]
+    elif r >= pts[-1][0]:
+        ceil = pts[-1][1]
+    else:
+        for (k0, v0), (k1, v1) in zip(pts, pts[1:]):
+            if k0 <= r <= k1:
+                ceil = v0 + (v1 - v0) * (r - k0) / (k1 - k0)
+                break
+    return {"writes_per_read": r, "ceiling_gbs": ceil, "frac": achieved_gbs / ceil,
+            "source": "spread_ceiling_gbs (k writes per read, 8 GiB written)"}
 
 
 def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
@@ -321,7 +349,8 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
     single_s = timed([])
     table_s = timed(buckets) if buckets else single_s
     step_s = min(single_s, table_s)
-    bpf = pool_bytes_per_frame(specs)
+    rd, wr = pool_rw_per_frame(specs)
+    bpf = rd + wr
     achieved = bpf * wl.n_envs / step_s / 1e9
     # baseline: each (H, W, mode, P) bucket as its own plain batch, one launch each per step
     keys = np.stack([specs["H"], specs["W"], specs["mode"], specs["P"]], 1)
@@ -361,7 +390,8 @@ def run_pool(gen, torch, steps: int, tune_it: bool) -> dict:
                                  "ms_per_step": bucket_s * 1e3},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": bpf,
-                         "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, step_s)}}
+                         "traffic": traffic_for(wl.name, wl.n_envs), "lds": lds_for(wl.name, step_s),
+                         "practical": practical(achieved, wr / rd)}}
 
 
 def served_roofline(frames_per_s: float, specs, key: str | None = None) -> dict:
@@ -370,10 +400,12 @@ def served_roofline(frames_per_s: float, specs, key: str | None = None) -> dict:
     group is a pool: descriptor read and step counter included).  With a
     counter record for `key` taken on the current kernel source, also the
     measured DRAM bytes per frame."""
-    bpf = pool_bytes_per_frame(specs)
+    rd, wr = pool_rw_per_frame(specs)
+    bpf = rd + wr
     ach = frames_per_s * bpf / 1e9
     out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-           "algorithmic_bytes_per_frame": bpf, "kernel": "k_serve", "traffic_bytes_per_frame": None}
+           "algorithmic_bytes_per_frame": bpf, "kernel": "k_serve", "traffic_bytes_per_frame": None,
+           "practical": practical(ach, wr / rd)}
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(key) if key else None
@@ -473,7 +505,8 @@ def run_plain_leg(gen, torch, wl, steps: int, warmup: int, obs_layout: int = 0) 
             "step_kernel_ms_mean": avg * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_frame": by["step"],
-                         "traffic": traffic_for(key, wl.n_envs), "lds": lds_for(key, avg)}}
+                         "traffic": traffic_for(key, wl.n_envs), "lds": lds_for(key, avg),
+                         "practical": practical(achieved, by["step_write"] / by["step_read"])}}
 
 
 def host_cores() -> int:
@@ -660,8 +693,12 @@ def main() -> int:
     if "copy" in legs:
         log("copy ceiling")
         out["roofline"]["copy_ceiling_gbs"] = copy_ceiling_gbs(gen, torch)
-        out["roofline"]["writes_per_read"] = by["step_write"] / by["step_read"]
-        out["roofline"]["spread_ceiling_gbs"] = spread_ceiling_gbs(gen, torch)
+        _SPREAD.update(spread_ceiling_gbs(gen, torch))
+        out["roofline"]["spread_ceiling_gbs"] = dict(_SPREAD)
+        out["roofline"]["practical"] = practical(achieved, by["step_write"] / by["step_read"])
+        if "sustained" in out:
+            out["sustained"]["practical"] = practical(by["step"] * E / (out["sustained"]["step_kernel_ms_mean"] / 1e3)
+                                                      / 1e9, by["step_write"] / by["step_read"])
     if "c1" in legs:
         # 16 envs of 10x10: 16 workgroups on 256 CUs, bound by launch latency, not bytes
         out["c1"] = run_plain_leg(gen, torch, workloads.C1, workloads.C1.steps, W)
