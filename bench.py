@@ -143,20 +143,21 @@ def copy_ceiling_gbs(gen, torch, n_bytes: int = 1 << 30, reps: int = 20) -> floa
     return gbs
 
 
-def spread_ceiling_gbs(gen, torch, ks=(1, 2, 3, 4, 5, 6, 8, 11), n_bytes: int = 8 << 30, reps: int = 20) -> dict:
+def spread_ceiling_gbs(gen, torch, ks=(0, 1, 2, 3, 4, 5, 6, 8, 11), n_bytes: int = 8 << 30, reps: int = 20) -> dict:
     """Bandwidth of the library's spread kernel (each 16-byte source chunk
     written to k destination chunks, the copy's form; read + write bytes /
     time) for k writes per read: the practical ceiling of a stream with a
     step's own mix of reads and writes (1v1 24x24 writes about 3.5 times
     what it reads, the mixed pool about 4.4, FFA-8 25x25 about 11).  8 GiB
     written, so that even the k = 11 source (745 MB) is well beyond the
-    256 MB Infinity Cache (at 1 GiB the sources of k >= 4 fit in it)."""
+    256 MB Infinity Cache (at 1 GiB the sources of k >= 4 fit in it).
+    k = 0: the write-only stream (zeros, nothing read)."""
     dst = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
     src = torch.empty(n_bytes, dtype=torch.uint8, device="cuda").fill_(1)
     stream = torch.cuda.current_stream()
     out = {}
     for k in ks:
-        n_src = -(-(n_bytes // 16) // k) * 16
+        n_src = -(-(n_bytes // 16) // k) * 16 if k else 0
         for _ in range(3):
             gen.gen_stream_spread(dst, src[:n_src], k, stream)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -287,7 +288,7 @@ def practical(achieved_gbs: float, writes_per_read: float):
     its points, the last point beyond them); None without the copy leg."""
     if not _SPREAD:
         return None
-    pts = sorted((int(k), v) for k, v in _SPREAD.items())
+    pts = sorted((int(k), v) for k, v in _SPREAD.items() if int(k) >= 1)
     r = writes_per_read
     if r <= pts[0][0]:
         ceil = pts[0][1]

@@ -540,8 +540,9 @@ int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream
  * stream writing k bytes per byte read: an env step writes 3.5 (1v1 24x24)
  * to 11 (FFA-8 25x25) times what it reads, so timed at the step's ratio it
  * gives the practical HBM ceiling of the step's mix of reads and writes.
- * GEN_EINVAL on a null or misaligned buffer, a bad size or k = 0.  Asynchronous
- * on `stream`. */
+ * k = 0 writes zeros and reads nothing (d_src may be NULL): a write-only
+ * stream.  GEN_EINVAL on a null or misaligned buffer or a bad size.
+ * Asynchronous on `stream`. */
 int gen_stream_spread(void *d_dst, const void *d_src, uint64_t dst_bytes, uint32_t k, void *stream);
 
 #ifdef __cplusplus

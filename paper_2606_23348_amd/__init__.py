@@ -322,10 +322,11 @@ def gen_stream_copy(dst, src, stream=None):
 
 def gen_stream_spread(dst, src, k: int, stream=None):
     """Chunk i (16 bytes) of dst = chunk i // k of src: k bytes written per
-    byte read (src holds at least ceil(chunks of dst / k) chunks)."""
+    byte read (src holds at least ceil(chunks of dst / k) chunks); k = 0
+    writes zeros and reads nothing (src may be None)."""
     n = dst.numel() * dst.element_size()
-    assert k >= 1 and src.numel() * src.element_size() * k >= n
-    _check(lib().gen_stream_spread(_ptr(dst), _ptr(src), n, k, _stream(stream)))
+    assert k == 0 or (k >= 1 and src.numel() * src.element_size() * k >= n)
+    _check(lib().gen_stream_spread(_ptr(dst), _ptr(src) if k else None, n, k, _stream(stream)))
 
 
 def gen_get_envs_static(st: gen_state, env_ids, stream=None) -> dict:

@@ -662,9 +662,9 @@ int gen_stream_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream
 
 int gen_stream_spread(void *d_dst, const void *d_src, uint64_t dst_bytes, uint32_t k, void *stream)
 {
-    if (d_dst == nullptr || d_src == nullptr || !aligned(d_dst, 16) || !aligned(d_src, 16) || dst_bytes % 16 != 0)
+    if (d_dst == nullptr || !aligned(d_dst, 16) || (k != 0 && (d_src == nullptr || !aligned(d_src, 16))) ||
+        dst_bytes % 16 != 0)
         return fail(GEN_EINVAL, "gen_stream_spread needs 16-byte aligned buffers and a multiple of 16 bytes");
-    if (k == 0) return fail(GEN_EINVAL, "gen_stream_spread needs k >= 1");
     if (dst_bytes / 16 > 0xFFFFFFFFull) return fail(GEN_EINVAL, "gen_stream_spread writes fewer than 2^32 chunks");
     if (dst_bytes == 0) return ok();
     hipError_t e = gen::launch_stream_spread(d_dst, d_src, (uint32_t)(dst_bytes / 16), k, static_cast<hipStream_t>(stream));

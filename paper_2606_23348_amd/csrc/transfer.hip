@@ -106,14 +106,15 @@ __global__ __launch_bounds__(256) void k_stream_copy(u32x4 *__restrict__ dst, co
     if (i < n16) __builtin_nontemporal_store(src[i], dst + i);
 }
 
-// dst[i] = src[i / k] (k >= 1, fewer than 2^32 elements): each source element
-// written to k consecutive destination elements, in the copy's form.  A
-// stream that writes k bytes for every byte it reads.
+// dst[i] = src[i / k] (fewer than 2^32 elements): each source element
+// written to k consecutive destination elements, in the copy's form; a
+// stream that writes k bytes for every byte it reads.  k = 0: zeros, no
+// reads (a write-only stream).
 __global__ __launch_bounds__(256) void k_stream_spread(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
                                                         uint32_t n16, uint32_t k)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n16) __builtin_nontemporal_store(src[i / k], dst + i);
+    if (i < n16) __builtin_nontemporal_store(k != 0 ? src[i / k] : u32x4{0u, 0u, 0u, 0u}, dst + i);
 }
 
 hipError_t launch_stream_spread(void *dst, const void *src, uint32_t n16, uint32_t k, hipStream_t stream)

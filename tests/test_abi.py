@@ -113,8 +113,8 @@ def test_stream_helpers_reject_bad_arguments(L):
     assert L.gen_stream_spread(a, None, 64, 2, None) == gen.GEN_EINVAL
     assert L.gen_stream_spread(a, ctypes.c_void_p((1 << 21) + 4), 64, 2, None) == gen.GEN_EINVAL
     assert L.gen_stream_spread(a, b, 40, 2, None) == gen.GEN_EINVAL
-    assert L.gen_stream_spread(a, b, 64, 0, None) == gen.GEN_EINVAL
-    assert "k >= 1" in gen.gen_last_error()
+    assert L.gen_stream_spread(None, b, 64, 0, None) == gen.GEN_EINVAL
+    assert L.gen_stream_spread(a, None, 40, 0, None) == gen.GEN_EINVAL
     assert L.gen_stream_spread(a, b, 16 << 32, 1, None) == gen.GEN_EINVAL       # 2^32 chunks
     assert L.gen_stream_spread(a, b, 0, 3, None) == gen.GEN_OK
 

@@ -46,3 +46,16 @@ def test_stream_spread(gen, k, chunks):
     got = buf.cpu().numpy()
     assert np.array_equal(got[:chunks * 16], expect)
     assert (got[chunks * 16:] == 0xAB).all()
+
+
+@pytest.mark.parametrize("chunks", [1, 300, 4099])
+def test_stream_spread_write_only(gen, chunks):
+    """k = 0: zeros written, nothing read (no source buffer)."""
+    import torch
+    buf = torch.full(((chunks + 32) * 16,), 0xAB, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    gen.gen_stream_spread(buf[:chunks * 16], None, 0)
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy()
+    assert not got[:chunks * 16].any()
+    assert (got[chunks * 16:] == 0xAB).all()
