@@ -704,6 +704,7 @@ def main() -> int:
         # 16 envs of 10x10: 16 workgroups on 256 CUs, bound by launch latency, not bytes
         out["c1"] = run_plain_leg(gen, torch, workloads.C1, workloads.C1.steps, W)
         out["c1"]["roofline"]["bound"] = "latency (16 workgroups)"
+        out["c1"]["roofline"]["practical"] = None
     if "c3" in legs:
         log("FFA-8 leg")
         out["c3"] = run_plain_leg(gen, torch, workloads.C3, max(K, 20), W, obs_layout=1)
