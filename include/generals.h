@@ -157,7 +157,8 @@ int gen_default_params(int32_t mode, int32_t n_players, gen_params *out);
 
 /* Compute the device layout of n_envs envs of H x W (3..32 each side) in
  * `mode` without touching the device.  params NULL = defaults.  Fills *out
- * (d_buf = NULL).  GEN_EINVAL on a bad shape, mode or parameter. */
+ * (d_buf = NULL).  GEN_EINVAL on a bad shape (n_envs < 1 included: an empty
+ * batch has no layout), mode or parameter. */
 int gen_layout(int32_t n_envs, int32_t H, int32_t W, int32_t mode, const gen_params *params,
                uint64_t seed, gen_state *out);
 
@@ -343,7 +344,7 @@ typedef struct gen_pool_bucket {
 /* Plan a pool of n_envs envs described by h_specs[n_envs] (host).  `common`
  * supplies the mountain threshold, city armies, auto_reset and pregrow
  * (NULL: defaults); its city counts, spawn distance and n_players are
- * ignored in favour of each spec. */
+ * ignored in favour of each spec.  GEN_EINVAL for n_envs < 1 or a bad spec. */
 int gen_pool_create(uint64_t seed, uint64_t env_base, int32_t n_envs, const gen_env_spec *h_specs,
                     const gen_params *common, gen_pool **out);
 int gen_pool_destroy(gen_pool *pool);

@@ -102,6 +102,18 @@ def test_calls_reject_missing_state_without_touching_the_device(L):
     assert L.gen_reset(1, 0, 4, 10, 10, 0, None, None, 0, None, None, None) == gen.GEN_EINVAL
 
 
+def test_empty_batches_are_rejected(L):
+    """An empty batch or pool has no layout: GEN_EINVAL before any device call."""
+    with pytest.raises(gen.GenError) as ei:
+        gen.gen_layout(0, 10, 10, gen.GEN_1V1)
+    assert ei.value.code == gen.GEN_EINVAL and "positive" in str(ei.value)
+    out = ctypes.c_void_p()
+    spec = (gen.gen_env_spec * 1)()
+    assert L.gen_pool_create(0, 0, 0, spec, None, ctypes.byref(out)) == gen.GEN_EINVAL
+    assert "positive" in gen.gen_last_error() and not out.value
+    assert L.gen_pool_create(0, 0, -3, spec, None, ctypes.byref(out)) == gen.GEN_EINVAL
+
+
 def test_stream_helpers_reject_bad_arguments(L):
     """The measurement copies check their arguments before any HIP call
     (the fake addresses are never dereferenced)."""

@@ -154,6 +154,7 @@ def test_c1_full_trajectory(gen):
     (19, 17, 2, 5, 20, 150),     # H*W = 3 mod 4 over two rounds; players 4.. draw from the second block
     (31, 31, 1, 4, 8, 100),      # H*W = 1 mod 4 over four rounds, 2v2
     (13, 9, 2, 7, 20, 150),      # FFA-7: the two waves of an env write 2 and 5 players' planes
+    (32, 32, 2, 8, 6, 120),      # the largest grid with the most players: 64 planes of 1,024 cells
 ])
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
@@ -170,6 +171,7 @@ def test_trajectory_parity(gen, H, W, mode, P, E, steps, fused):
     (31, 31, 1, 4, 8, 100),      # 2v2, H*W = 1 mod 4
     (3, 3, 0, 2, 64, 200),       # tiny grid: one quad of map cells, seven of padding
     (8, 4, 0, 2, 16, 100),       # H*W = 32: padded and dense layouts coincide
+    (32, 32, 2, 8, 6, 120),      # the largest grid with the most players
 ])
 @pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
 def test_trajectory_parity_padded_planes(gen, H, W, mode, P, E, steps, fused):
