@@ -174,14 +174,19 @@ __device__ __forceinline__ Rsrc buffer_rsrc(void *base, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kRawWord3);
 }
 
-// Inclusive prefix sum over the wave (lane order).
+// Inclusive prefix sum over the wave (lane order), in DPP moves: shifts by
+// 1, 2, 4 and 8 lanes within each row of 16 (lanes shifted in from outside
+// the row add 0), then the last lane of row 0 added to row 1 and that of
+// row 2 to row 3, then the last lane of row 1 added to rows 2 and 3.  Every
+// lane of the wave must be active.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = lane_id();
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = shfl32(v, lane - d);
-        if (lane >= d) v += o;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15, rows 1 and 3
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31, rows 2 and 3
     return v;
 }
 

@@ -451,16 +451,33 @@ __device__ void actor_wave(const Geom &g, const uint64_t *own, const uint64_t *p
         const uint32_t idx = pick(r, 1u + total);
         const bool mine = valid && idx > 0 && excl <= idx - 1 && idx - 1 < excl + cnt;
         if (mine) {
-            const uint32_t t = idx - 1 - excl;
+            // entry t of this word lies in the last cell b whose earlier cells
+            // hold at most t entries.  A cell's move count n = lu + ld + ll + lr
+            // (0..4) as three bit planes, n = s0 + 2 s1 + 4 s2 (full adders; a
+            // carry of the second level excludes those of the first), so the
+            // entries of a set of cells are 2 (|s0| + 2 |s1| + 4 |s2|); the
+            // search halves the word, then works on 32-bit halves.
+            uint32_t t = idx - 1 - excl;
+            const uint64_t xa = lu ^ ld, xb = ll ^ lr, c1 = lu & ld, c2 = ll & lr;
+            const uint64_t s0 = xa ^ xb, c3 = xa & xb;
+            const uint64_t s1 = c1 ^ c2 ^ c3, s2 = c1 & c2;
+            uint32_t h0 = (uint32_t)s0, h1 = (uint32_t)s1, h2 = (uint32_t)s2;
+            const uint32_t lo = 2u * (uint32_t)(__popc(h0) + 2 * __popc(h1) + 4 * __popc(h2));
             int b = 0;
-            for (int st = 32; st >= 1; st >>= 1) {
-                const uint64_t m = (1ull << (b + st)) - 1ull;
-                const uint32_t pre = 2u * (uint32_t)(__popcll(lu & m) + __popcll(ld & m) + __popcll(ll & m) +
-                                                     __popcll(lr & m));
-                if (pre <= t) b += st;
+            if (lo <= t) {
+                b = 32;
+                t -= lo;
+                h0 = (uint32_t)(s0 >> 32); h1 = (uint32_t)(s1 >> 32); h2 = (uint32_t)(s2 >> 32);
             }
-            const uint64_t m = (1ull << b) - 1ull;
-            uint32_t j = t - 2u * (uint32_t)(__popcll(lu & m) + __popcll(ld & m) + __popcll(ll & m) + __popcll(lr & m));
+            int bl = 0;
+            for (int st = 16; st >= 1; st >>= 1) {
+                const uint32_t m = (1u << (bl + st)) - 1u;
+                const uint32_t pre = 2u * (uint32_t)(__popc(h0 & m) + 2 * __popc(h1 & m) + 4 * __popc(h2 & m));
+                if (pre <= t) bl += st;
+            }
+            b += bl;
+            const uint32_t ml = (1u << bl) - 1u;
+            uint32_t j = t - 2u * (uint32_t)(__popc(h0 & ml) + 2 * __popc(h1 & ml) + 4 * __popc(h2 & ml));
             const uint32_t dirs = (uint32_t)((lu >> b) & 1ull) | ((uint32_t)((ld >> b) & 1ull) << 1) |
                                   ((uint32_t)((ll >> b) & 1ull) << 2) | ((uint32_t)((lr >> b) & 1ull) << 3);
             const uint32_t nd = (uint32_t)__popc(dirs);
