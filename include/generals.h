@@ -188,7 +188,7 @@ int gen_reset(uint64_t seed, uint64_t env_base, int32_t n_envs, int32_t H, int32
 int gen_step(const gen_state *st, const int32_t *d_actions, uint8_t *d_obs, int32_t *d_rewards,
              uint8_t *d_dones, int32_t *d_land, int64_t *d_army, void *stream);
 
-/* Random legal actor (the benchmark driver; the paper fixes no generator):
+/* Random legal actor (the action source of the benchmarks; the paper fixes no generator):
  * for every env, player p takes 32-bit word p mod 4 of the Philox4x32-10
  * block with key (actor_seed low, actor_seed high) and counter (step_idx
  * low, step_idx high, env low, env high), env = env_base + e, the counter's
