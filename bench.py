@@ -468,7 +468,7 @@ def run_served_mix(gen, torch, duration_s: float) -> dict:
             "frames_per_s": rep["frames"] / rep["wall_s"], "requests": rep["requests"],
             "lat_p50_us": rep["lat_p50_us"], "lat_p99_us": rep["lat_p99_us"],
             "envs_per_launch": rep["envs_per_launch"], "launches": rep["launches"], "wall_s": rep["wall_s"],
-            "roofline": served_roofline(rep["frames"] / rep["wall_s"], specs)}
+            "roofline": served_roofline(rep["frames"] / rep["wall_s"], specs, "served-" + wl.name)}
 
 
 LAYOUT_NAMES = {0: "dense [E,P,8,H,W]", 1: "planes padded to 32 bytes (64 above 2 players)"}
